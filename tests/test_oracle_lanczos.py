@@ -1,0 +1,164 @@
+"""Pins for the oracle's Haydock-Lanczos chain and continued fraction
+(Eqs. ai-ci, fraccont, epsmacro)."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import tbinputs as ti
+
+from _cases import bands, oracle_operator, oracle_parts, rel_l2
+
+CFG = ti.tiny_config(n_coarse=2, n_div=2, nv=2, nc=2, n_pol=3)          # N = 256
+CFG2 = ti.tiny_config(n_coarse=3, n_div=2, nv=2, nc=2, n_pol=2, seed=3)  # N = 864
+
+
+def _lorentz_l2(eps, ref):
+    return rel_l2(eps.imag, ref.imag)
+
+
+@pytest.mark.parametrize("cfg", [CFG, CFG2], ids=lambda c: c.name)
+def test_full_chain_continued_fraction_equals_diagonalisation(cfg):
+    op = oracle_operator(cfg)
+    H = op.explicit_hamiltonian()
+    P = bands(cfg).P_flat()
+    om = np.linspace(0, 16, 801)
+    ch = O.haydock(lambda x: (H @ x.T).T, P, op.N, reorth=True, tol=1e-10)
+    eps = O.continued_fraction(ch["a"], ch["b"], ch["pnorm2"], cfg.prefactor(), om, 0.1,
+                               ch["steps"])
+    ref = O.eigh_spectrum(H, P, cfg.prefactor(), om, 0.1)
+    assert _lorentz_l2(eps, ref) < 1e-10
+    assert rel_l2(eps.real - 1, ref.real - 1) < 1e-10
+
+
+def test_zero_kernel_gives_independent_particle_spectrum():
+    bs, Dv, Dc, f, Kc, delta = oracle_parts(CFG)
+    op = oracle_operator(CFG, Kc=np.zeros_like(Kc))
+    P = bs.P_flat()
+    om = np.linspace(0, 16, 801)
+    ch = O.haydock(op.apply, P, op.N, reorth=True, tol=1e-10)
+    eps = O.continued_fraction(ch["a"], ch["b"], ch["pnorm2"], CFG.prefactor(), om, 0.1,
+                               ch["steps"])
+    ref = O.ip_spectrum(delta, P, CFG.prefactor(), om, 0.1)
+    assert _lorentz_l2(eps, ref) < 1e-10
+
+
+def test_plain_chain_matches_reorthogonalised_chain_early_steps():
+    op = oracle_operator(CFG2)
+    P = bands(CFG2).P_flat()
+    c1 = O.haydock(op.apply, P, 30)
+    c2 = O.haydock(op.apply, P, 30, reorth=True)
+    np.testing.assert_allclose(c1["a"], c2["a"], rtol=1e-10)
+    np.testing.assert_allclose(c1["b"], c2["b"], rtol=1e-10)
+
+
+def test_moments_of_the_tridiagonal_matrix():
+    """<P|H^k|P> = ||P||^2 (T^k)_{11} for k <= 2m - 1."""
+    op = oracle_operator(CFG)
+    P = bands(CFG).P_flat()[:1]
+    m = 6
+    ch = O.haydock(op.apply, P, m)
+    a, b = ch["a"][0], ch["b"][0]
+    T = np.diag(a) + np.diag(b[1:m], 1) + np.diag(b[1:m], -1)
+    v = P.copy()
+    scale = np.abs(op.delta).max() * 2
+    for k in range(1, 2 * m):
+        v = op.apply(v)
+        mom = np.vdot(P, v).real
+        tk = np.linalg.matrix_power(T, k)[0, 0] * ch["pnorm2"][0]
+        assert abs(mom - tk) <= 1e-11 * scale ** k * ch["pnorm2"][0]
+
+
+def test_ritz_values_inside_spectrum_and_unit_vectors():
+    op = oracle_operator(CFG)
+    H = op.explicit_hamiltonian()
+    E = np.linalg.eigvalsh(H)
+    P = bands(CFG).P_flat()
+    ch = O.haydock(op.apply, P, 40)
+    for r in range(P.shape[0]):
+        m = ch["steps"][r]
+        T = np.diag(ch["a"][r, :m]) + np.diag(ch["b"][r, 1:m], 1) + np.diag(ch["b"][r, 1:m], -1)
+        ritz = np.linalg.eigvalsh(T)
+        assert ritz.min() >= E.min() - 1e-10 and ritz.max() <= E.max() + 1e-10
+
+
+def test_spectral_shift_moves_a_only():
+    op = oracle_operator(CFG)
+    P = bands(CFG).P_flat()
+    sigma = 2.75
+    # exact in exact arithmetic; this 256-dimensional case exhausts its well-conditioned
+    # Krylov directions after about 18 steps, so the pin covers the first 15
+    c1 = O.haydock(op.apply, P, 15)
+    c2 = O.haydock(lambda x: op.apply(x) + sigma * x, P, 15)
+    np.testing.assert_allclose(c2["a"], c1["a"] + sigma, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(c2["b"], c1["b"], rtol=0, atol=1e-12)
+
+
+def test_breakdown_on_eigenvector_start_is_exact():
+    op = oracle_operator(CFG)
+    H = op.explicit_hamiltonian()
+    E, V = np.linalg.eigh(H)
+    P = 3.0 * V[:, 7][None]
+    ch = O.haydock(lambda x: (H @ x.T).T, P, 10)
+    assert ch["steps"][0] == 1
+    assert abs(ch["a"][0, 0] - E[7]) < 1e-12
+    om = np.linspace(0, 16, 101)
+    eps = O.continued_fraction(ch["a"], ch["b"], ch["pnorm2"], 1.0, om, 0.1, ch["steps"])
+    np.testing.assert_allclose(eps[0], 1.0 - 9.0 / (om + 0.1j - E[7]), rtol=1e-12)
+
+
+def test_zero_start_vector():
+    op = oracle_operator(CFG)
+    ch = O.haydock(op.apply, np.zeros((1, op.N)), 5)
+    assert ch["steps"][0] == 0 and ch["pnorm2"][0] == 0
+    eps = O.continued_fraction(ch["a"], ch["b"], ch["pnorm2"], 1.0, np.linspace(0, 1, 5), 0.1,
+                               ch["steps"])
+    assert np.all(eps == 1.0)
+
+
+def test_two_level_fraction_is_a_two_pole_lorentzian():
+    """m = 2: the fraction equals the pole sum of the 2x2 Jacobi matrix."""
+    a = np.array([[1.3, 4.1]])
+    b = np.array([[0.0, 0.7, 0.0]])
+    T = np.array([[1.3, 0.7], [0.7, 4.1]])
+    E, V = np.linalg.eigh(T)
+    om = np.linspace(0, 6, 61)
+    z = om + 0.05j
+    ref = 1.0 - 2.5 * 1.7 * np.sum(np.abs(V[0])[:, None] ** 2 / (z[None] - E[:, None]), axis=0)
+    eps = O.continued_fraction(a, b, [1.7], 2.5, om, 0.05)
+    np.testing.assert_allclose(eps[0], ref, rtol=1e-13)
+
+
+def test_gauge_invariance_of_chain_coefficients():
+    """Phases on the dense and coarse bands (P transformed with them) leave a_n, b_n
+    unchanged."""
+    cfg = CFG2
+    bs = bands(cfg)
+    rng = np.random.default_rng(31)
+    th = np.exp(1j * rng.uniform(0, 2 * np.pi, size=bs.vecs_dense.shape[:2]))
+    vd = bs.vecs_dense * th[..., None]
+    vc = vd[::cfg.n_div3].copy()
+    Dv, Dc = O.overlaps(vc, vd, cfg.n_coarse, cfg.n_div, cfg.nv, cfg.nc)
+    Kc = O.coarse_kernel(vc, bs.tau, cfg.nv, cfg.nc, cfg.n_coarse, cfg.n_div, cfg)
+    delta = O.transition_energies(bs.eps_dense, cfg.nv, cfg.nc)
+    op2 = O.InterpOperator(Dv, Dc, O.trilinear_weights(cfg.n_div), Kc, delta, cfg.n_coarse,
+                           cfg.n_div, cfg.nv, cfg.nc)
+    # P_vck = <c|dH|v>/de picks up conj(t_c) t_v
+    u = (th[:, :cfg.nv, None] * np.conj(th[:, None, cfg.nv:cfg.nv + cfg.nc])).reshape(-1)
+    P2 = bs.P_flat() * u[None]
+    c1 = O.haydock(oracle_operator(cfg).apply, bs.P_flat(), 30)
+    c2 = O.haydock(op2.apply, P2, 30)
+    np.testing.assert_allclose(c2["a"], c1["a"], rtol=1e-11)
+    np.testing.assert_allclose(c2["b"], c1["b"], rtol=1e-11)
+
+
+def test_c0_chain_is_stable_and_spectrum_positive():
+    cfg = ti.get_config("c0")
+    op = oracle_operator(cfg)
+    P = bands(cfg).P_flat()
+    ch = O.haydock(op.apply, P, cfg.steps)
+    assert ch["steps"][0] == cfg.steps
+    assert np.all(np.isfinite(ch["a"])) and np.all(ch["b"][0, 1:] > 0)
+    eps = O.continued_fraction(ch["a"], ch["b"], ch["pnorm2"], cfg.prefactor(), cfg.omega(),
+                               cfg.eta)
+    assert np.all(eps.imag > 0)
