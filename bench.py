@@ -1,0 +1,202 @@
+"""Benchmark: Haydock steps/s of the double-grid on-the-fly BSE path on one MI355X.
+
+Workload (default): 8^3 coarse mesh, 4 divisions per axis (32^3 = 32768 dense k),
+3 valence + 6 conduction bands (N = 589,824 transitions), coarse kernel 9216^2
+complex FP32, 3 polarisations advanced together, FP64 accumulation and Lanczos
+scalars.  A step is one Haydock iteration of all three chains: coarse product,
+prolong + diagonal + a_i, update + restrict + b_{i+1}, collapse.  Inputs are
+seeded synthetic tight-binding data, resident in HBM before timing starts.
+
+Prints one JSON line (see the keys below).  The CPU baseline times the plain
+FP64 oracle on the host for a bounded number of steps of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP32_VALU_TFLOPS = 157.3       # published vector FP32 peak
+
+
+def _args():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=300)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--config", default="c1")
+    p.add_argument("--dtype", default=None, help="f32 | f32v64 | f64 (default: workload's)")
+    p.add_argument("--splits", type=int, default=0, help="column splits of the coarse product (0 = auto)")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-steps", type=int, default=8, help="oracle steps timed for the CPU baseline")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="also run a plain 1 GiB device copy (for HBM counter calibration)")
+    return p.parse_args()
+
+
+def main():
+    args = _args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
+              "the multi-GPU layout is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import tbinputs as ti
+    from paper_1602_01863_amd import bse
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfg = ti.get_config(args.config)
+    dtype = args.dtype or {"c128": "f64", "c64": "f32"}[cfg.dtype]
+    t0 = time.perf_counter()
+    bs = ti.band_structure(cfg)
+    t_inputs = time.perf_counter() - t0
+
+    # ---- setup on the device (overlaps, transition energies, coarse kernel, plan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob = bse.problem_from_bands(bs, cfg, dtype=dtype, max_rhs=cfg.n_pol)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    if args.splits:
+        bse.bse_plan_set_gemv_splits(prob.plan, args.splits)
+    P = torch.as_tensor(bs.P_flat()).to("cuda").contiguous()
+
+    # ---- warmup, then exactly K timed steps (one chain run of K steps)
+    if args.warmup > 0:
+        prob.haydock(P, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch = prob.haydock(P, args.steps)
+    torch.cuda.synchronize()
+    t_chain = time.perf_counter() - t0
+    ms_per_step = 1e3 * t_chain / args.steps
+    steps_per_s = args.steps / t_chain
+
+    # ---- dominant kernel (coarse product): HIP events around each launch, same stream
+    prob.set_timing(True)
+    torch.cuda.synchronize()
+    prob.haydock(P, args.steps)
+    torch.cuda.synchronize()
+    gemv_ms_total, gemv_launches = prob.timing()
+    prob.set_timing(False)
+    gemv_ms = gemv_ms_total / max(1, gemv_launches)
+    Nc, n_rhs = prob.Nc, cfg.n_pol
+    mat_bytes = 8 if dtype in ("f32", "f32v64") else 16
+    gemv_bytes = Nc * Nc * mat_bytes + 2 * Nc * n_rhs * 16      # K_c once + qbar in + r out
+    gemv_flops = 8.0 * Nc * Nc * n_rhs                           # complex MAC = 8 flops
+    achieved_gbs = gemv_bytes / (gemv_ms * 1e-3) / 1e9
+
+    # ---- time to eps2 on the host from a ready plan (chain + continued fraction + copy)
+    om = cfg.omega()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch2 = prob.haydock(P, cfg.steps)
+    eps = prob.continued_fraction(ch2, cfg.prefactor(), om, cfg.eta)
+    eps_host = eps.cpu().numpy()
+    t_eps = time.perf_counter() - t0
+    status = ch2["status"].cpu().numpy().tolist()
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    # ---- algorithmic bytes of a whole step (for the step-level bandwidth)
+    N, ncell, ndiv3 = prob.N, cfg.nk_coarse, cfg.n_div3
+    ne = cfg.nv ** 2 + cfg.nc ** 2
+    vec_bytes = 8 if dtype == "f32" else 16
+    d_bytes = ncell * 8 * ne * ndiv3 * mat_bytes
+    step_bytes = (gemv_bytes + 2 * d_bytes                    # K_c; overlaps in prolong and restrict
+                  + n_rhs * N * vec_bytes * 6                  # psi_i x2, psi_{i-1}, w write/read, u write
+                  + N * 8)                                     # transition energies (FP64)
+    out = {
+        "metric": "Haydock steps/s",
+        "value": round(steps_per_s, 2),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if dtype == "f32" else ("f32/f64-vectors" if dtype == "f32v64" else "f64"),
+        "data": "synthetic (seeded tight-binding crystal)",
+        "config": {
+            "workload": (f"{cfg.name}: {cfg.n_coarse}^3 coarse x {cfg.n_div}^3 divisions "
+                         f"({cfg.nk_dense} dense k), {cfg.nv}v+{cfg.nc}c, N={N}, Kc {Nc}^2, "
+                         f"{n_rhs} polarisations per step, {dtype} storage, FP64 accumulation"),
+            "n_coarse": cfg.n_coarse, "n_div": cfg.n_div, "nv": cfg.nv, "nc": cfg.nc, "N": N,
+            "N_coarse": Nc, "polarisations": n_rhs, "parallelism": "single GPU",
+        },
+        "chain_steps_per_s": round(steps_per_s * n_rhs, 2),
+        "step_algorithmic_bytes": int(step_bytes),
+        "step_GBps": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+        "coarse_product": {
+            "avg_ms": round(gemv_ms, 5), "launches": gemv_launches,
+            "TFLOPs": round(gemv_flops / (gemv_ms * 1e-3) / 1e12, 3),
+            "engine": "VALU FP64 FMA on FP32 storage (HBM-bound; no MFMA)",
+        },
+        "roofline": {
+            "kernel": "k_gemv (coarse product r = K_c qbar)",
+            "bound": "hbm",
+            "achieved": round(achieved_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+            "traffic": None,
+        },
+        "time_to_eps2_s": round(t_eps, 4),
+        "setup_s": round(t_setup, 3),
+        "inputs_s": round(t_inputs, 2),
+        "chain_status": status,
+        "eps2_peak": float(np.max(eps_host.imag)),
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, bs, args.cpu_steps)
+    prob.close()
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(cfg, bs, n_steps):
+    """Time the plain FP64 oracle's Haydock steps on the host (same workload)."""
+    import numpy as np
+
+    import oracle as O
+
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    Dv, Dc = O.overlaps(bs.vecs_coarse, bs.vecs_dense, cfg.n_coarse, cfg.n_div, cfg.nv, cfg.nc)
+    Kc = O.coarse_kernel(bs.vecs_coarse, bs.tau, cfg.nv, cfg.nc, cfg.n_coarse, cfg.n_div, cfg)
+    delta = O.transition_energies(bs.eps_dense, cfg.nv, cfg.nc)
+    op = O.InterpOperator(Dv, Dc, O.trilinear_weights(cfg.n_div), Kc, delta, cfg.n_coarse, cfg.n_div,
+                          cfg.nv, cfg.nc)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.haydock(op.apply, bs.P_flat(), n_steps)
+    t = time.perf_counter() - t0
+    return {"value": round(n_steps / t, 4), "unit": "steps/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"{n_steps} Haydock steps of the same workload (all {cfg.n_pol} polarisations per "
+                       f"step) with the FP64 NumPy oracle, after its untimed setup of {t_setup:.0f} s "
+                       f"(overlaps, coarse kernel)")}
+
+
+if __name__ == "__main__":
+    main()

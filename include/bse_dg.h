@@ -1,0 +1,219 @@
+/*
+ * bse_dg.h - C ABI of the double-grid on-the-fly BSE / Haydock library (gfx950).
+ *
+ * The library applies the dense-mesh Tamm-Dancoff BSE Hamiltonian whose kernel
+ * is interpolated on the fly from a coarse-mesh kernel (Gillet, Giantomassi,
+ * Gonze, "Efficient on-the-fly interpolation technique for Bethe-Salpeter
+ * calculations of optical spectra", Sec. 4, Eqs. matmul1-matmul3), runs the
+ * Haydock-Lanczos recursion on it (Sec. 2, Eqs. ai-ci) and evaluates the
+ * continued fraction for the macroscopic dielectric function (Eq. fraccont).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Meshes (Sec. 3): a cubic coarse mesh of n_coarse points per axis and n_div
+ * divisions per axis.  Coarse point / cell index cell = (i1 n + i2) n + i3;
+ * subpoint sub = (j1 n_div + j2) n_div + j3; dense point kd = cell n_div^3 + sub
+ * (cell-major).  Corner z = 4 l + 2 m + n is the coarse point
+ * (i1 + l, i2 + m, i3 + n), indices wrapping periodically.
+ * Transitions: dense t = (kd nv + v) nc + c; coarse T = (cell nv + n1) nc + n2,
+ * N = n_coarse^3 n_div^3 nv nc, Nc = n_coarse^3 nv nc.
+ * Complex numbers are interleaved (re, im) pairs of the storage precision.
+ * Vectors with several right-hand sides are stored column by column:
+ * element (t, r) at offset r * N + t.
+ *
+ * Memory: every pointer documented "device" must point to device memory of the
+ * current HIP device; "host" pointers to host memory.  The library never
+ * allocates device memory: scratch space is the caller's workspace.  All
+ * device work is enqueued on the given stream, in stream order, and the calls
+ * return without waiting for it unless stated otherwise.
+ *
+ * Errors: calls return a bse_status.  Negative values are errors and nothing
+ * was enqueued (argument checks happen before any launch) unless the value is
+ * BSE_ERR_HIP, which reports a failed HIP call; bse_last_error() then gives a
+ * message (thread-local, valid until the next call on the same thread).
+ */
+#ifndef BSE_DG_H
+#define BSE_DG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BSE_OK = 0,
+    BSE_INFO_INVARIANT_SUBSPACE = 1, /* chain status: b_{i+1} vanished, chain complete */
+    BSE_INFO_ZERO_START = 2,         /* chain status: ||P|| = 0, eps_M = 1 */
+    BSE_ERR_INVALID_ARG = -1,
+    BSE_ERR_HIP = -2,
+    BSE_ERR_NONFINITE = -3,          /* chain status: a_i or b_{i+1} not finite */
+    BSE_ERR_UNSUPPORTED = -4,        /* band counts or precision not compiled in */
+    BSE_ERR_WORKSPACE = -5           /* workspace missing, misaligned or too small */
+} bse_status;
+
+/* Storage precision of the coarse kernel, the overlaps and the Lanczos
+ * vectors.  Every sum (restrict, coarse product, prolong, dot products) is
+ * accumulated in FP64 whatever the storage. */
+typedef enum {
+    BSE_F64 = 0,       /* kernel, overlaps, vectors: complex FP64 */
+    BSE_F32 = 1,       /* kernel, overlaps, vectors: complex FP32 */
+    BSE_F32_VEC64 = 2  /* kernel, overlaps: complex FP32; Lanczos vectors: complex FP64 */
+} bse_dtype;
+
+typedef struct {
+    int32_t n_coarse;   /* coarse points per axis (Sec. 3, k~ mesh), >= 1 */
+    int32_t n_div;      /* divisions per axis (n_1 = n_2 = n_3 = n_div, Sec. 3), >= 1 */
+    int32_t nv;         /* valence bands of the transition space */
+    int32_t nc;         /* conduction bands of the transition space */
+    int32_t n_orb;      /* orbital-basis size of the band-structure input (builders only) */
+    int32_t max_rhs;    /* largest number of right-hand sides per call, 1..4 */
+    int32_t dtype;      /* bse_dtype */
+    int32_t neighbours; /* 8: trilinear prefactors (Sec. 3, Eq. interpwfn);
+                           1: nearest corner only (Rohlfing-Louie, Eq. eqRL) */
+} bse_dims;
+
+typedef struct bse_plan bse_plan; /* opaque, host object owned by the library */
+
+/* Parameters of the model kernel built by bse_build_coarse_kernel. */
+typedef struct {
+    double eps_inf;        /* screening of W(Q) = 4 pi / (eps_inf |Q|^2 + lambda^2) */
+    double lambda;         /* screening wavevector */
+    double kernel_energy;  /* energy scale; K_c = kernel_energy / N_k(dense) (2X - D) */
+    int32_t g2_max;        /* plane waves: integer G with |G|^2 <= g2_max */
+    int32_t q0_quad;       /* midpoint points per axis for the q -> 0 average of W */
+} bse_kernel_model;
+
+/* Library version string (static storage). */
+const char* bse_version(void);
+
+/* Message of the last error on this thread ("" if none). */
+const char* bse_last_error(void);
+
+/* Bytes of device workspace a plan for dims needs (0 if dims is invalid).
+ * The workspace must be 256-byte aligned. */
+size_t bse_workspace_bytes(const bse_dims* dims);
+
+/* Bytes of one coarse kernel (Nc x Nc complex) and of the overlap array for dims. */
+size_t bse_coarse_kernel_bytes(const bse_dims* dims);
+size_t bse_overlaps_bytes(const bse_dims* dims);
+
+/*
+ * Overlaps d_{nk}^{n'k~} = <u_{n'k~} | u_{nk}> between each dense point and its
+ * 8 coarse corners (Sec. 3, Eq. completeness); only valence-valence and
+ * conduction-conduction blocks (Eq. expansion).
+ *   vecs_coarse  device, complex FP64 [n_coarse^3][nv+nc][n_orb]: coefficient a of
+ *                band n at coarse point k~ (bands 0..nv-1 valence, then nc conduction)
+ *   vecs_dense   device, complex FP64 [N_k(dense)][nv+nc][n_orb], same layout
+ *   d_out        device, storage precision of dims->dtype, bse_overlaps_bytes(dims)
+ *                bytes, layout [cell][z][e][sub] with e < nv^2 the valence block
+ *                Dv[v][n1] at e = v nv + n1 and e >= nv^2 the conduction block
+ *                Dc[c][n2] at e = nv^2 + c nc + n2 (n1, n2 index coarse bands).
+ */
+bse_status bse_build_overlaps(const bse_dims* dims, const double* vecs_coarse,
+                              const double* vecs_dense, void* d_out, hipStream_t stream);
+
+/*
+ * Diagonal of Eq. (bse1): delta[t] = eps_{c kd} - eps_{v kd} (FP64).
+ *   eps_dense  device FP64 [N_k(dense)][nv+nc] band energies (scissor included)
+ *   delta_out  device FP64 [N]
+ */
+bse_status bse_build_transition_energies(const bse_dims* dims, const double* eps_dense,
+                                         double* delta_out, hipStream_t stream);
+
+/*
+ * Coarse kernel K_c = kernel_energy / N_k(dense) (2 X - D) (Eqs. bse2, bse3a, bse3b),
+ * for point-like orbitals at reduced positions tau in a cubic cell of lattice
+ * constant 1, pair densities M_nm(k,k';Q) = sum_a conj(c_{nk,a}) c_{mk',a}
+ * exp(i 2 pi Q.tau_a), exchange X over G != 0 with v = 4 pi / |2 pi G|^2 and
+ * direct term D with W = 4 pi / (eps_inf |2 pi (q + G)|^2 + lambda^2),
+ * q = k~ - k~' folded into [-1/2, 1/2) per axis, W at q = G = 0 replaced by its
+ * mean over the dense mini-cell.  Block (k~, k~') is evaluated for k~ <= k~', its
+ * mirror is the conjugate transpose and diagonal blocks are (A + A^H)/2, so the
+ * result is exactly Hermitian.
+ *   vecs_coarse  device, complex FP64 [n_coarse^3][nv+nc][n_orb]
+ *   tau          device FP64 [n_orb][3]
+ *   Kc_out       device, storage precision, row-major Nc x Nc complex
+ */
+bse_status bse_build_coarse_kernel(const bse_dims* dims, const double* vecs_coarse,
+                                   const double* tau, const bse_kernel_model* model,
+                                   void* Kc_out, hipStream_t stream);
+
+/*
+ * Plan: binds the inputs of the interpolated Hamiltonian H^i = diag(delta) + K^i
+ * (Eqs. bse1, interp1) and a workspace.  The arrays are referenced, not copied:
+ * they must stay valid and unchanged while the plan is used.
+ *   Kc         device, Nc x Nc complex (storage precision), row-major, Hermitian:
+ *              the product reads it by columns and uses Kc[j][i] = conj(Kc[i][j])
+ *   d          device, overlaps in the layout of bse_build_overlaps
+ *   delta      device FP64 [N]
+ *   workspace  device, >= bse_workspace_bytes(dims) bytes, 256-byte aligned; owned
+ *              by the plan until bse_plan_destroy; one plan must not run on two
+ *              streams at once.
+ * Zeroes the workspace counters on `stream`.
+ */
+bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d,
+                           const double* delta, void* workspace, size_t workspace_bytes,
+                           hipStream_t stream, bse_plan** plan_out);
+void bse_plan_destroy(bse_plan* plan);
+
+/*
+ * y = H^i x for n_rhs right-hand sides (Eq. bse1 diagonal plus Eqs. matmul1-matmul3:
+ * restrict onto per-(cell, corner) coarse vectors, collapse them onto coarse
+ * points, multiply by K_c, prolong back with the diagonal added).
+ *   x, y   device, storage precision of the Lanczos vectors, N x n_rhs; x != y
+ *   n_rhs  1 .. max_rhs
+ */
+bse_status bse_interp_matvec(bse_plan* plan, const void* x, void* y, int32_t n_rhs,
+                             hipStream_t stream);
+
+/*
+ * Haydock-Lanczos chains (Eqs. ai-ci), one per right-hand side, all steps on
+ * the device without host synchronisation: b_1 = 0, psi_1 = P/||P||, then
+ * w = H psi_i - b_i psi_{i-1}, a_i = Re<psi_i|w>, b_{i+1} = ||w - a_i psi_i||,
+ * psi_{i+1} = (w - a_i psi_i) / b_{i+1}.  Scalars in FP64.
+ *   P          device, complex FP64, N x n_rhs (oscillator matrix elements, Eq. epsmacro)
+ *   n_steps    chain length m >= 1
+ *   a          device FP64 [n_rhs][n_steps]:   a[r*n_steps + i] = a_{i+1}
+ *   b          device FP64 [n_rhs][n_steps+1]: b[r*(n_steps+1) + i] = b_{i+1}, b_1 = 0
+ *   pnorm2     device FP64 [n_rhs]: ||P||^2
+ *   steps_done device int32 [n_rhs]: valid a_i per chain
+ *   status     device int32 [n_rhs]: BSE_OK, BSE_INFO_INVARIANT_SUBSPACE (b_{i+1} <=
+ *              tol ||w||, the chain stops there), BSE_INFO_ZERO_START or
+ *              BSE_ERR_NONFINITE; coefficients past steps_done are 0.
+ */
+bse_status bse_haydock_run(bse_plan* plan, const double* P, int32_t n_rhs, int32_t n_steps,
+                           double* a, double* b, double* pnorm2, int32_t* steps_done,
+                           int32_t* status, hipStream_t stream);
+
+/*
+ * eps_M(omega) = 1 - prefactor ||P||^2 / (z - a_1 - b_2^2 / (z - a_2 - ...)),
+ * z = omega + i eta, truncated after a_m with m = steps[chain] (Eq. fraccont).
+ * All pointers device; chains are stored with leading dimensions lda (a) and
+ * ldb (b) as returned by bse_haydock_run (lda = n_steps, ldb = n_steps + 1).
+ *   eps_re, eps_im  device FP64 [n_chains][n_omega]
+ */
+bse_status bse_continued_fraction(const double* a, const double* b, int32_t lda, int32_t ldb,
+                                  const double* pnorm2, const int32_t* steps,
+                                  int32_t n_chains, double prefactor, const double* omega,
+                                  int32_t n_omega, double eta, double* eps_re, double* eps_im,
+                                  hipStream_t stream);
+
+/* Kernel timing: when enabled, the plan records HIP events around every launch
+ * of the coarse product (the dominant kernel) on the stream it is launched on.
+ * bse_plan_get_timing synchronises those events and returns the total time in
+ * milliseconds and the number of timed launches since the last reset. */
+bse_status bse_plan_set_timing(bse_plan* plan, int32_t enable);
+bse_status bse_plan_get_timing(bse_plan* plan, double* total_ms, int64_t* launches);
+
+/* Tunables of the coarse product: column splits (0 = automatic).  For sweeps. */
+bse_status bse_plan_set_gemv_splits(bse_plan* plan, int32_t n_split);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSE_DG_H */

@@ -1,0 +1,320 @@
+"""Python binding of libbse_dg.so (ctypes).
+
+Functions named like the C entry points marshal torch device tensors into raw
+pointers and call the library; they compute nothing themselves.  Device memory
+and streams come from PyTorch.  ``BSEProblem`` wires the setup calls, the plan
+and its workspace together for one Hamiltonian.
+
+The library must have been built (``__graft_entry__.build()`` or
+``python -m paper_1602_01863_amd.build``); importing this module without it
+raises, there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbse_dg.so")
+
+BSE_OK = 0
+BSE_INFO_INVARIANT_SUBSPACE = 1
+BSE_INFO_ZERO_START = 2
+BSE_ERR_INVALID_ARG = -1
+BSE_ERR_HIP = -2
+BSE_ERR_NONFINITE = -3
+BSE_ERR_UNSUPPORTED = -4
+BSE_ERR_WORKSPACE = -5
+
+BSE_F64, BSE_F32, BSE_F32_VEC64 = 0, 1, 2
+DTYPES = {"f64": BSE_F64, "f32": BSE_F32, "f32v64": BSE_F32_VEC64}
+
+# symbols declared in include/bse_dg.h
+EXPORTED = [
+    "bse_version", "bse_last_error", "bse_workspace_bytes", "bse_coarse_kernel_bytes",
+    "bse_overlaps_bytes", "bse_build_overlaps", "bse_build_transition_energies",
+    "bse_build_coarse_kernel", "bse_plan_create", "bse_plan_destroy", "bse_interp_matvec",
+    "bse_haydock_run", "bse_continued_fraction", "bse_plan_set_timing", "bse_plan_get_timing",
+    "bse_plan_set_gemv_splits",
+]
+
+
+class BSEError(RuntimeError):
+    pass
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("n_coarse", ctypes.c_int32), ("n_div", ctypes.c_int32), ("nv", ctypes.c_int32),
+                ("nc", ctypes.c_int32), ("n_orb", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("neighbours", ctypes.c_int32)]
+
+
+class KernelModel(ctypes.Structure):
+    _fields_ = [("eps_inf", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("kernel_energy", ctypes.c_double), ("g2_max", ctypes.c_int32),
+                ("q0_quad", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise BSEError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    P = ctypes.POINTER
+    sig = {
+        "bse_version": (ctypes.c_char_p, []),
+        "bse_last_error": (ctypes.c_char_p, []),
+        "bse_workspace_bytes": (sz, [P(Dims)]),
+        "bse_coarse_kernel_bytes": (sz, [P(Dims)]),
+        "bse_overlaps_bytes": (sz, [P(Dims)]),
+        "bse_build_overlaps": (i32, [P(Dims), vp, vp, vp, vp]),
+        "bse_build_transition_energies": (i32, [P(Dims), vp, vp, vp]),
+        "bse_build_coarse_kernel": (i32, [P(Dims), vp, vp, P(KernelModel), vp, vp]),
+        "bse_plan_create": (i32, [P(Dims), vp, vp, vp, vp, sz, vp, P(vp)]),
+        "bse_plan_destroy": (None, [vp]),
+        "bse_interp_matvec": (i32, [vp, vp, vp, i32, vp]),
+        "bse_haydock_run": (i32, [vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]),
+        "bse_continued_fraction": (i32, [vp, vp, i32, i32, vp, vp, i32, dbl, vp, i32, dbl, vp, vp, vp]),
+        "bse_plan_set_timing": (i32, [vp, i32]),
+        "bse_plan_get_timing": (i32, [vp, P(dbl), P(i64)]),
+        "bse_plan_set_gemv_splits": (i32, [vp, i32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def library() -> ctypes.CDLL:
+    return _lib
+
+
+def _check(status: int, what: str) -> int:
+    if status < 0:
+        msg = _lib.bse_last_error().decode(errors="replace")
+        raise BSEError(f"{what} failed with status {status}: {msg}")
+    return status
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+# ---- thin wrappers with the C names ---------------------------------------------------
+def bse_version() -> str:
+    return _lib.bse_version().decode()
+
+
+def bse_workspace_bytes(dims: Dims) -> int:
+    return int(_lib.bse_workspace_bytes(ctypes.byref(dims)))
+
+
+def bse_coarse_kernel_bytes(dims: Dims) -> int:
+    return int(_lib.bse_coarse_kernel_bytes(ctypes.byref(dims)))
+
+
+def bse_overlaps_bytes(dims: Dims) -> int:
+    return int(_lib.bse_overlaps_bytes(ctypes.byref(dims)))
+
+
+def bse_build_overlaps(dims, vecs_coarse, vecs_dense, d_out, stream=None):
+    _check(_lib.bse_build_overlaps(ctypes.byref(dims), _ptr(vecs_coarse), _ptr(vecs_dense), _ptr(d_out),
+                                   _stream(stream)), "bse_build_overlaps")
+
+
+def bse_build_transition_energies(dims, eps_dense, delta_out, stream=None):
+    _check(_lib.bse_build_transition_energies(ctypes.byref(dims), _ptr(eps_dense), _ptr(delta_out),
+                                              _stream(stream)), "bse_build_transition_energies")
+
+
+def bse_build_coarse_kernel(dims, vecs_coarse, tau, model: KernelModel, Kc_out, stream=None):
+    _check(_lib.bse_build_coarse_kernel(ctypes.byref(dims), _ptr(vecs_coarse), _ptr(tau), ctypes.byref(model),
+                                        _ptr(Kc_out), _stream(stream)), "bse_build_coarse_kernel")
+
+
+def bse_plan_create(dims, Kc, d, delta, workspace, stream=None):
+    plan = ctypes.c_void_p()
+    _check(_lib.bse_plan_create(ctypes.byref(dims), _ptr(Kc), _ptr(d), _ptr(delta), _ptr(workspace),
+                                workspace.numel() * workspace.element_size(), _stream(stream),
+                                ctypes.byref(plan)), "bse_plan_create")
+    return plan
+
+
+def bse_plan_destroy(plan):
+    _lib.bse_plan_destroy(plan)
+
+
+def bse_interp_matvec(plan, x, y, n_rhs, stream=None):
+    _check(_lib.bse_interp_matvec(plan, _ptr(x), _ptr(y), int(n_rhs), _stream(stream)), "bse_interp_matvec")
+
+
+def bse_haydock_run(plan, P, n_rhs, n_steps, a, b, pnorm2, steps_done, status, stream=None):
+    _check(_lib.bse_haydock_run(plan, _ptr(P), int(n_rhs), int(n_steps), _ptr(a), _ptr(b), _ptr(pnorm2),
+                                _ptr(steps_done), _ptr(status), _stream(stream)), "bse_haydock_run")
+
+
+def bse_continued_fraction(a, b, lda, ldb, pnorm2, steps, n_chains, prefactor, omega, n_omega, eta,
+                           eps_re, eps_im, stream=None):
+    _check(_lib.bse_continued_fraction(_ptr(a), _ptr(b), int(lda), int(ldb), _ptr(pnorm2), _ptr(steps),
+                                       int(n_chains), float(prefactor), _ptr(omega), int(n_omega), float(eta),
+                                       _ptr(eps_re), _ptr(eps_im), _stream(stream)), "bse_continued_fraction")
+
+
+def bse_plan_set_timing(plan, enable: bool):
+    _check(_lib.bse_plan_set_timing(plan, int(bool(enable))), "bse_plan_set_timing")
+
+
+def bse_plan_get_timing(plan):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(_lib.bse_plan_get_timing(plan, ctypes.byref(ms), ctypes.byref(n)), "bse_plan_get_timing")
+    return ms.value, n.value
+
+
+def bse_plan_set_gemv_splits(plan, n_split: int):
+    _check(_lib.bse_plan_set_gemv_splits(plan, int(n_split)), "bse_plan_set_gemv_splits")
+
+
+# ---- one Hamiltonian on the device ------------------------------------------------------
+def _storage(dtype_code: int):
+    """(matrix complex dtype, vector complex dtype) for a bse_dtype."""
+    if dtype_code == BSE_F64:
+        return torch.complex128, torch.complex128
+    if dtype_code == BSE_F32:
+        return torch.complex64, torch.complex64
+    return torch.complex64, torch.complex128
+
+
+class BSEProblem:
+    """Device-resident inputs, setup products and a plan for one Hamiltonian.
+
+    vecs_coarse [Nkc, nv+nc, n_orb], vecs_dense [Nk, nv+nc, n_orb] (complex128),
+    eps_dense [Nk, nv+nc] (eV), tau [n_orb, 3]; all numpy arrays or tensors.
+    """
+
+    def __init__(self, n_coarse, n_div, nv, nc, vecs_coarse, vecs_dense, eps_dense, tau, *,
+                 dtype="f64", max_rhs=1, neighbours=8, eps_inf=12.0, lam=0.3, kernel_energy=6.0,
+                 g2_max=4, q0_quad=16, device="cuda", Kc=None, d=None):
+        self.device = torch.device(device)
+        n_orb = int(np.shape(vecs_dense)[-1])
+        self.dims = Dims(n_coarse, n_div, nv, nc, n_orb, max_rhs, DTYPES[dtype], neighbours)
+        self.model = KernelModel(eps_inf, lam, kernel_energy, g2_max, q0_quad)
+        self.mat_dtype, self.vec_dtype = _storage(self.dims.dtype)
+        self.nk = n_coarse ** 3 * n_div ** 3
+        self.N = self.nk * nv * nc
+        self.Nc = n_coarse ** 3 * nv * nc
+        dev = self.device
+        as_t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a) if isinstance(a, np.ndarray) else a,
+                                             dtype=dt).to(dev).contiguous()
+        self.vecs_coarse = as_t(vecs_coarse, torch.complex128)
+        self.vecs_dense = as_t(vecs_dense, torch.complex128)
+        self.eps_dense = as_t(eps_dense, torch.float64)
+        self.tau = as_t(tau, torch.float64)
+        ne = (nv * nv + nc * nc)
+        self.d = torch.empty(n_coarse ** 3 * 8 * ne * n_div ** 3, dtype=self.mat_dtype, device=dev)
+        assert self.d.numel() * self.d.element_size() == bse_overlaps_bytes(self.dims)
+        self.Kc = torch.empty(self.Nc, self.Nc, dtype=self.mat_dtype, device=dev)
+        assert self.Kc.numel() * self.Kc.element_size() == bse_coarse_kernel_bytes(self.dims)
+        self.delta = torch.empty(self.N, dtype=torch.float64, device=dev)
+        if d is None:
+            bse_build_overlaps(self.dims, self.vecs_coarse, self.vecs_dense, self.d)
+        else:
+            self.d.copy_(torch.as_tensor(d).to(dev).reshape(-1))
+        bse_build_transition_energies(self.dims, self.eps_dense, self.delta)
+        if Kc is None:
+            bse_build_coarse_kernel(self.dims, self.vecs_coarse, self.tau, self.model, self.Kc)
+        else:
+            self.Kc.copy_(torch.as_tensor(Kc).to(dev).reshape(self.Nc, self.Nc))
+        nbytes = bse_workspace_bytes(self.dims)
+        if nbytes == 0:
+            raise BSEError(_lib.bse_last_error().decode())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.plan = bse_plan_create(self.dims, self.Kc, self.d, self.delta, self.workspace)
+
+    def close(self):
+        if getattr(self, "plan", None) is not None:
+            bse_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- products ----------------------------------------------------------------------
+    def vector(self, x) -> torch.Tensor:
+        """[n_rhs, N] device vector in the plan's vector storage."""
+        t = torch.as_tensor(x)
+        if t.dim() == 1:
+            t = t[None]
+        return t.to(self.device).to(self.vec_dtype).contiguous()
+
+    def matvec(self, x) -> torch.Tensor:
+        x = self.vector(x)
+        y = torch.empty_like(x)
+        bse_interp_matvec(self.plan, x, y, x.shape[0])
+        return y
+
+    def haydock(self, P, n_steps: int) -> dict:
+        P = torch.as_tensor(P)
+        if P.dim() == 1:
+            P = P[None]
+        P = P.to(self.device).to(torch.complex128).contiguous()
+        r = P.shape[0]
+        dev = self.device
+        a = torch.empty(r, n_steps, dtype=torch.float64, device=dev)
+        b = torch.empty(r, n_steps + 1, dtype=torch.float64, device=dev)
+        pn = torch.empty(r, dtype=torch.float64, device=dev)
+        steps = torch.empty(r, dtype=torch.int32, device=dev)
+        status = torch.empty(r, dtype=torch.int32, device=dev)
+        bse_haydock_run(self.plan, P, r, n_steps, a, b, pn, steps, status)
+        return dict(a=a, b=b, pnorm2=pn, steps=steps, status=status)
+
+    @staticmethod
+    def continued_fraction(chain: dict, prefactor: float, omega, eta: float) -> torch.Tensor:
+        a, b = chain["a"], chain["b"]
+        dev = a.device
+        om = torch.as_tensor(np.asarray(omega, dtype=np.float64)).to(dev)
+        n_chains = a.shape[0]
+        er = torch.empty(n_chains, om.numel(), dtype=torch.float64, device=dev)
+        ei = torch.empty_like(er)
+        bse_continued_fraction(a, b, a.shape[1], b.shape[1], chain["pnorm2"], chain["steps"], n_chains,
+                               prefactor, om, om.numel(), eta, er, ei)
+        return torch.complex(er, ei)
+
+    def set_timing(self, enable: bool):
+        bse_plan_set_timing(self.plan, enable)
+
+    def timing(self):
+        return bse_plan_get_timing(self.plan)
+
+
+def problem_from_bands(bs, cfg, dtype=None, max_rhs=None, neighbours=8, **kw) -> BSEProblem:
+    """BSEProblem for a tbinputs BandStructure and its config."""
+    if dtype is None:
+        dtype = {"c128": "f64", "c64": "f32"}.get(cfg.dtype, cfg.dtype)
+    return BSEProblem(cfg.n_coarse, cfg.n_div, cfg.nv, cfg.nc, bs.vecs_coarse, bs.vecs_dense, bs.eps_dense,
+                      bs.tau, dtype=dtype, max_rhs=max_rhs or cfg.n_pol, neighbours=neighbours,
+                      eps_inf=cfg.eps_inf, lam=cfg.lam, kernel_energy=cfg.kernel_energy, g2_max=cfg.g2_max,
+                      q0_quad=cfg.q0_quad, **kw)

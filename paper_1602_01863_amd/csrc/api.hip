@@ -1,0 +1,436 @@
+// C ABI of the double-grid BSE library: argument checks, workspace layout and
+// the stream-ordered drivers of the matvec and of the Haydock chain.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "bse_device.hpp"
+#include "bse_plan.hpp"
+
+namespace bse {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+static bse_status hip_fail(hipError_t e, const char* what) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return BSE_ERR_HIP;
+}
+
+bool make_geometry(const bse_dims* d, Geometry* g) {
+    if (!d) {
+        set_error("dims is NULL");
+        return false;
+    }
+    if (d->n_coarse < 1 || d->n_coarse > 64 || d->n_div < 1 || d->n_div > 16) {
+        set_error("n_coarse must be in [1, 64] and n_div in [1, 16]");
+        return false;
+    }
+    if (d->nv < 1 || d->nc < 1) {
+        set_error("nv and nc must be positive");
+        return false;
+    }
+    if (d->max_rhs < 1 || d->max_rhs > kMaxRhs) {
+        set_error("max_rhs must be in [1, %d]", kMaxRhs);
+        return false;
+    }
+    if (d->dtype != BSE_F64 && d->dtype != BSE_F32 && d->dtype != BSE_F32_VEC64) {
+        set_error("unknown dtype %d", d->dtype);
+        return false;
+    }
+    if (d->neighbours != 8 && d->neighbours != 1) {
+        set_error("neighbours must be 8 or 1");
+        return false;
+    }
+    g->n_c = d->n_coarse;
+    g->n_div = d->n_div;
+    g->ndiv3 = d->n_div * d->n_div * d->n_div;
+    g->ncells = d->n_coarse * d->n_coarse * d->n_coarse;
+    g->nv = d->nv;
+    g->nc = d->nc;
+    g->np = d->nv * d->nc;
+    g->ne = d->nv * d->nv + d->nc * d->nc;
+    g->neighbours = d->neighbours;
+    g->dtype = d->dtype;
+    g->n_orb_input = d->n_orb;
+    g->nk = (int64_t)g->ncells * g->ndiv3;
+    g->N = g->nk * g->np;
+    g->Nc = (int64_t)g->ncells * g->np;
+    g->max_rhs = d->max_rhs;
+    if (g->Nc > (int64_t)1 << 30) {
+        set_error("coarse transition space too large");
+        return false;
+    }
+    return true;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static size_t vec_elem_bytes(int dtype) { return dtype == BSE_F32 ? sizeof(float2) : sizeof(double2); }
+static size_t mat_elem_bytes(int dtype) { return dtype == BSE_F64 ? sizeof(double2) : sizeof(float2); }
+
+Layout make_layout(const Geometry& g) {
+    Layout L;
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const size_t R = (size_t)g.max_rhs;
+    L.qpart = take((size_t)g.ncells * 8 * R * g.np * sizeof(double2));
+    L.qbar = take((size_t)g.Nc * R * sizeof(double2));
+    L.rvec = take((size_t)g.Nc * R * sizeof(double2));
+    L.gpart = take((size_t)kMaxSplit * g.Nc * R * sizeof(double2));
+    L.ppart = take((size_t)g.ncells * R * 2 * sizeof(double));
+    L.rpart = take((size_t)g.ncells * R * 2 * sizeof(double));
+    L.chain = take((size_t)kMaxRhs * sizeof(ChainState));
+    // counters, contiguous: one per row block of the product, then prolong, then restrict
+    const size_t nrowblk = (size_t)(g.Nc + 127) / 128;
+    L.gcount = take(nrowblk * sizeof(unsigned int));
+    L.pcount = take(sizeof(unsigned int));
+    L.rcount = take(sizeof(unsigned int));
+    L.vec_a = take((size_t)g.N * R * vec_elem_bytes(g.dtype));
+    L.vec_b = take((size_t)g.N * R * vec_elem_bytes(g.dtype));
+    L.total = off;
+    return L;
+}
+
+hipError_t launch_zero_counters(const Plan& p, hipStream_t s);
+
+// ---- continued fraction (Eq. fraccont) ------------------------------------------------
+__global__ __launch_bounds__(256) void k_continued_fraction(const double* __restrict__ a, const double* __restrict__ b,
+                                                            int lda, int ldb, const double* __restrict__ pnorm2,
+                                                            const int32_t* __restrict__ steps, int n_chains,
+                                                            double prefactor, const double* __restrict__ omega,
+                                                            int n_omega, double eta, double* __restrict__ eps_re,
+                                                            double* __restrict__ eps_im) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_chains * n_omega) return;
+    const int ch = (int)(i / n_omega);
+    const int w = (int)(i % n_omega);
+    const int m = min(steps[ch], lda);
+    const double pn = pnorm2[ch];
+    if (m <= 0 || pn == 0.0) {
+        eps_re[i] = 1.0;
+        eps_im[i] = 0.0;
+        return;
+    }
+    const double zr = omega[w], zi = eta;
+    const double* ac = a + (int64_t)ch * lda;
+    const double* bc = b + (int64_t)ch * ldb;
+    // t_m = z - a_m; t_i = z - a_i - b_{i+1}^2 / t_{i+1}
+    double tr = zr - ac[m - 1], ti = zi;
+    for (int j = m - 2; j >= 0; --j) {
+        const double b2 = bc[j + 1] * bc[j + 1];
+        const double den = tr * tr + ti * ti;
+        const double ur = b2 * tr / den, ui = -b2 * ti / den;   // b^2 / t
+        tr = zr - ac[j] - ur;
+        ti = zi - ui;
+    }
+    // eps = 1 - C ||P||^2 / t
+    const double den = tr * tr + ti * ti;
+    const double cr = prefactor * pn * tr / den, ci = -prefactor * pn * ti / den;
+    eps_re[i] = 1.0 - cr;
+    eps_im[i] = -ci;
+}
+
+hipError_t launch_continued_fraction(const double* a, const double* b, int lda, int ldb, const double* pnorm2,
+                                     const int32_t* steps, int n_chains, double prefactor, const double* omega,
+                                     int n_omega, double eta, double* eps_re, double* eps_im, hipStream_t s) {
+    const int64_t total = (int64_t)n_chains * n_omega;
+    const int nb = (int)((total + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_continued_fraction, dim3(nb), dim3(kBlock), 0, s, a, b, lda, ldb, pnorm2, steps, n_chains,
+                       prefactor, omega, n_omega, eta, eps_re, eps_im);
+    return hipGetLastError();
+}
+
+}  // namespace bse
+
+using namespace bse;
+
+extern "C" {
+
+const char* bse_version(void) { return "bse-dg 0.1.0 (gfx950)"; }
+
+const char* bse_last_error(void) { return g_err; }
+
+size_t bse_workspace_bytes(const bse_dims* dims) {
+    Geometry g;
+    if (!make_geometry(dims, &g)) return 0;
+    return make_layout(g).total;
+}
+
+size_t bse_coarse_kernel_bytes(const bse_dims* dims) {
+    Geometry g;
+    if (!make_geometry(dims, &g)) return 0;
+    return (size_t)g.Nc * (size_t)g.Nc * mat_elem_bytes(g.dtype);
+}
+
+size_t bse_overlaps_bytes(const bse_dims* dims) {
+    Geometry g;
+    if (!make_geometry(dims, &g)) return 0;
+    return (size_t)g.ncells * 8 * g.ne * g.ndiv3 * mat_elem_bytes(g.dtype);
+}
+
+bse_status bse_build_overlaps(const bse_dims* dims, const double* vecs_coarse, const double* vecs_dense,
+                              void* d_out, hipStream_t stream) {
+    Geometry g;
+    if (!make_geometry(dims, &g)) return BSE_ERR_INVALID_ARG;
+    if (!vecs_coarse || !vecs_dense || !d_out) {
+        set_error("bse_build_overlaps: NULL pointer");
+        return BSE_ERR_INVALID_ARG;
+    }
+    if (g.n_orb_input < 1) {
+        set_error("bse_build_overlaps: n_orb must be positive");
+        return BSE_ERR_INVALID_ARG;
+    }
+    hipError_t e = launch_overlaps(g, vecs_coarse, vecs_dense, d_out, stream);
+    return e == hipSuccess ? BSE_OK : hip_fail(e, "bse_build_overlaps");
+}
+
+bse_status bse_build_transition_energies(const bse_dims* dims, const double* eps_dense, double* delta_out,
+                                         hipStream_t stream) {
+    Geometry g;
+    if (!make_geometry(dims, &g)) return BSE_ERR_INVALID_ARG;
+    if (!eps_dense || !delta_out) {
+        set_error("bse_build_transition_energies: NULL pointer");
+        return BSE_ERR_INVALID_ARG;
+    }
+    hipError_t e = launch_transition_energies(g, eps_dense, delta_out, stream);
+    return e == hipSuccess ? BSE_OK : hip_fail(e, "bse_build_transition_energies");
+}
+
+bse_status bse_build_coarse_kernel(const bse_dims* dims, const double* vecs_coarse, const double* tau,
+                                   const bse_kernel_model* model, void* Kc_out, hipStream_t stream) {
+    Geometry g;
+    if (!make_geometry(dims, &g)) return BSE_ERR_INVALID_ARG;
+    if (!vecs_coarse || !tau || !model || !Kc_out) {
+        set_error("bse_build_coarse_kernel: NULL pointer");
+        return BSE_ERR_INVALID_ARG;
+    }
+    if (g.n_orb_input < 1 || g.n_orb_input > 16 || g.nv + g.nc > 16 || g.np > 32) {
+        set_error("bse_build_coarse_kernel: needs n_orb <= 16, nv + nc <= 16, nv * nc <= 32");
+        return BSE_ERR_UNSUPPORTED;
+    }
+    if (model->g2_max < 0 || model->g2_max > 4 || model->q0_quad < 1 || model->q0_quad > 256 ||
+        !(model->eps_inf > 0) || !(model->lambda >= 0)) {
+        set_error("bse_build_coarse_kernel: model parameters out of range (g2_max <= 4)");
+        return BSE_ERR_INVALID_ARG;
+    }
+    hipError_t e = launch_coarse_kernel(g, vecs_coarse, tau, *model, Kc_out, stream);
+    return e == hipSuccess ? BSE_OK : hip_fail(e, "bse_build_coarse_kernel");
+}
+
+bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d, const double* delta,
+                           void* workspace, size_t workspace_bytes, hipStream_t stream, bse_plan** plan_out) {
+    if (!plan_out) {
+        set_error("bse_plan_create: plan_out is NULL");
+        return BSE_ERR_INVALID_ARG;
+    }
+    *plan_out = nullptr;
+    Geometry g;
+    if (!make_geometry(dims, &g)) return BSE_ERR_INVALID_ARG;
+    if (!supported_bands(g.nv, g.nc)) {
+        set_error("bands nv=%d nc=%d are not compiled in", g.nv, g.nc);
+        return BSE_ERR_UNSUPPORTED;
+    }
+    if (!Kc || !d || !delta) {
+        set_error("bse_plan_create: NULL input array");
+        return BSE_ERR_INVALID_ARG;
+    }
+    Layout L = make_layout(g);
+    if (!workspace || ((uintptr_t)workspace & 255) != 0 || workspace_bytes < L.total) {
+        set_error("bse_plan_create: workspace must be 256-byte aligned and >= %zu bytes", L.total);
+        return BSE_ERR_WORKSPACE;
+    }
+    Plan* p = new (std::nothrow) Plan();
+    if (!p) {
+        set_error("bse_plan_create: out of host memory");
+        return BSE_ERR_INVALID_ARG;
+    }
+    p->g = g;
+    p->L = L;
+    p->Kc = Kc;
+    p->d = d;
+    p->delta = delta;
+    p->ws = static_cast<char*>(workspace);
+    p->n_split = 0;
+    p->timing = false;
+    p->ev = nullptr;
+    p->ev_cap = 0;
+    p->ev_used = 0;
+    p->timed_ms = 0.0;
+    p->timed_launches = 0;
+    hipError_t e = launch_zero_counters(*p, stream);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "bse_plan_create");
+    }
+    *plan_out = reinterpret_cast<bse_plan*>(p);
+    return BSE_OK;
+}
+
+static void release_events(Plan* p) {
+    if (p->ev) {
+        for (int i = 0; i < p->ev_cap; ++i) (void)hipEventDestroy(p->ev[i]);
+        delete[] p->ev;
+    }
+    p->ev = nullptr;
+    p->ev_cap = 0;
+    p->ev_used = 0;
+}
+
+void bse_plan_destroy(bse_plan* plan) {
+    if (!plan) return;
+    Plan* p = reinterpret_cast<Plan*>(plan);
+    release_events(p);
+    delete p;
+}
+
+bse_status bse_interp_matvec(bse_plan* plan, const void* x, void* y, int32_t n_rhs, hipStream_t stream) {
+    if (!plan || !x || !y) {
+        set_error("bse_interp_matvec: NULL argument");
+        return BSE_ERR_INVALID_ARG;
+    }
+    Plan& p = *reinterpret_cast<Plan*>(plan);
+    if (n_rhs < 1 || n_rhs > p.g.max_rhs) {
+        set_error("bse_interp_matvec: n_rhs must be in [1, %d]", p.g.max_rhs);
+        return BSE_ERR_INVALID_ARG;
+    }
+    if (x == y) {
+        set_error("bse_interp_matvec: x and y must not alias");
+        return BSE_ERR_INVALID_ARG;
+    }
+    hipError_t e = launch_restrict(p, RESTRICT_PLAIN, x, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr,
+                                   0, 0, n_rhs, stream);
+    if (e == hipSuccess) e = launch_collapse(p, n_rhs, false, stream);
+    if (e == hipSuccess) e = launch_gemv(p, n_rhs, stream);
+    if (e == hipSuccess) e = launch_prolong(p, PROLONG_PLAIN, x, y, 0, nullptr, nullptr, 0, 0, n_rhs, stream);
+    return e == hipSuccess ? BSE_OK : hip_fail(e, "bse_interp_matvec");
+}
+
+bse_status bse_haydock_run(bse_plan* plan, const double* P, int32_t n_rhs, int32_t n_steps, double* a, double* b,
+                           double* pnorm2, int32_t* steps_done, int32_t* status, hipStream_t stream) {
+    if (!plan || !P || !a || !b || !pnorm2 || !steps_done || !status) {
+        set_error("bse_haydock_run: NULL argument");
+        return BSE_ERR_INVALID_ARG;
+    }
+    Plan& p = *reinterpret_cast<Plan*>(plan);
+    if (n_rhs < 1 || n_rhs > p.g.max_rhs || n_steps < 1) {
+        set_error("bse_haydock_run: n_rhs must be in [1, %d] and n_steps >= 1", p.g.max_rhs);
+        return BSE_ERR_INVALID_ARG;
+    }
+    const int lda = n_steps, ldb = n_steps + 1;
+    void* A = p.ws + p.L.vec_a;  // u_{i-1}, then w, then u_{i+1}
+    void* B = p.ws + p.L.vec_b;  // u_i
+    // u_1 = P, ||P||, coarse vector of psi_1; zero-fills a and b
+    hipError_t e = launch_restrict(p, RESTRICT_INIT, nullptr, nullptr, nullptr, P, B, 0, a, b, lda, ldb, n_rhs,
+                                   stream);
+    if (e == hipSuccess) e = launch_collapse(p, n_rhs, true, stream);
+    for (int i = 0; i < n_steps && e == hipSuccess; ++i) {
+        e = launch_gemv(p, n_rhs, stream);
+        if (e == hipSuccess) e = launch_prolong(p, PROLONG_LANCZOS, B, A, i, a, b, lda, ldb, n_rhs, stream);
+        if (e == hipSuccess)
+            e = launch_restrict(p, RESTRICT_UPDATE, nullptr, A, B, nullptr, A, i, a, b, lda, ldb, n_rhs, stream);
+        if (e == hipSuccess && i + 1 < n_steps) e = launch_collapse(p, n_rhs, true, stream);
+        std::swap(A, B);
+    }
+    if (e == hipSuccess) e = launch_chain_report(p, pnorm2, steps_done, status, n_rhs, stream);
+    return e == hipSuccess ? BSE_OK : hip_fail(e, "bse_haydock_run");
+}
+
+bse_status bse_continued_fraction(const double* a, const double* b, int32_t lda, int32_t ldb, const double* pnorm2,
+                                  const int32_t* steps, int32_t n_chains, double prefactor, const double* omega,
+                                  int32_t n_omega, double eta, double* eps_re, double* eps_im, hipStream_t stream) {
+    if (!a || !b || !pnorm2 || !steps || !omega || !eps_re || !eps_im) {
+        set_error("bse_continued_fraction: NULL argument");
+        return BSE_ERR_INVALID_ARG;
+    }
+    if (n_chains < 1 || n_omega < 1 || lda < 1 || ldb < lda + 1 || !(eta > 0)) {
+        set_error("bse_continued_fraction: need n_chains, n_omega >= 1, ldb >= lda + 1, eta > 0");
+        return BSE_ERR_INVALID_ARG;
+    }
+    hipError_t e = launch_continued_fraction(a, b, lda, ldb, pnorm2, steps, n_chains, prefactor, omega, n_omega,
+                                             eta, eps_re, eps_im, stream);
+    return e == hipSuccess ? BSE_OK : hip_fail(e, "bse_continued_fraction");
+}
+
+bse_status bse_plan_set_timing(bse_plan* plan, int32_t enable) {
+    if (!plan) {
+        set_error("bse_plan_set_timing: NULL plan");
+        return BSE_ERR_INVALID_ARG;
+    }
+    Plan& p = *reinterpret_cast<Plan*>(plan);
+    if (enable && !p.ev) {
+        const int cap = 4096;
+        p.ev = new (std::nothrow) hipEvent_t[cap];
+        if (!p.ev) {
+            set_error("bse_plan_set_timing: out of host memory");
+            return BSE_ERR_INVALID_ARG;
+        }
+        for (int i = 0; i < cap; ++i) {
+            hipError_t e = hipEventCreate(&p.ev[i]);
+            if (e != hipSuccess) {
+                p.ev_cap = i;
+                release_events(&p);
+                return hip_fail(e, "bse_plan_set_timing");
+            }
+        }
+        p.ev_cap = cap;
+    }
+    if (!enable) release_events(&p);
+    p.timing = enable != 0;
+    p.ev_used = 0;
+    p.timed_ms = 0.0;
+    p.timed_launches = 0;
+    return BSE_OK;
+}
+
+bse_status bse_plan_get_timing(bse_plan* plan, double* total_ms, int64_t* launches) {
+    if (!plan || !total_ms || !launches) {
+        set_error("bse_plan_get_timing: NULL argument");
+        return BSE_ERR_INVALID_ARG;
+    }
+    Plan& p = *reinterpret_cast<Plan*>(plan);
+    double ms = 0.0;
+    for (int i = 0; i + 1 < p.ev_used; i += 2) {
+        hipError_t e = hipEventSynchronize(p.ev[i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "bse_plan_get_timing");
+        float t = 0.0f;
+        e = hipEventElapsedTime(&t, p.ev[i], p.ev[i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "bse_plan_get_timing");
+        ms += t;
+    }
+    p.timed_ms += ms;
+    p.timed_launches += p.ev_used / 2;
+    p.ev_used = 0;
+    *total_ms = p.timed_ms;
+    *launches = p.timed_launches;
+    p.timed_ms = 0.0;
+    p.timed_launches = 0;
+    return BSE_OK;
+}
+
+bse_status bse_plan_set_gemv_splits(bse_plan* plan, int32_t n_split) {
+    if (!plan || n_split < 0 || n_split > kMaxSplit) {
+        set_error("bse_plan_set_gemv_splits: n_split must be in [0, %d]", kMaxSplit);
+        return BSE_ERR_INVALID_ARG;
+    }
+    reinterpret_cast<Plan*>(plan)->n_split = n_split;
+    return BSE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+// Device-side helpers shared by the kernels of the double-grid BSE library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bse {
+
+constexpr int kWave = 64;
+
+// ---- complex arithmetic in FP64 --------------------------------------------------
+struct cd {
+    double re, im;
+};
+
+__device__ __forceinline__ cd cmake(double r, double i) { return cd{r, i}; }
+__device__ __forceinline__ cd cadd(cd a, cd b) { return cd{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cd csub(cd a, cd b) { return cd{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cd cscale(cd a, double s) { return cd{a.re * s, a.im * s}; }
+__device__ __forceinline__ cd cconj(cd a) { return cd{a.re, -a.im}; }
+// acc += a * b
+__device__ __forceinline__ void cfma(cd& acc, cd a, cd b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(a.im, b.re, acc.im);
+}
+// acc += conj(a) * b
+__device__ __forceinline__ void cfma_cj(cd& acc, cd a, cd b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(-a.im, b.re, acc.im);
+}
+// acc += a * conj(b)
+__device__ __forceinline__ void cfma_jc(cd& acc, cd a, cd b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(a.im, b.im, acc.re);
+    acc.im = fma(a.im, b.re, acc.im);
+    acc.im = fma(-a.re, b.im, acc.im);
+}
+
+// ---- storage precision ------------------------------------------------------------
+template <class S>
+struct cstore;
+template <>
+struct cstore<double> {
+    using t2 = double2;
+};
+template <>
+struct cstore<float> {
+    using t2 = float2;
+};
+
+__device__ __forceinline__ cd ld(const double2* p) {
+    double2 v = *p;
+    return cd{v.x, v.y};
+}
+__device__ __forceinline__ cd ld(const float2* p) {
+    float2 v = *p;
+    return cd{(double)v.x, (double)v.y};
+}
+__device__ __forceinline__ void st(double2* p, cd v) { *p = make_double2(v.re, v.im); }
+__device__ __forceinline__ void st(float2* p, cd v) { *p = make_float2((float)v.re, (float)v.im); }
+// value after a round trip through the storage type
+__device__ __forceinline__ cd rounded(cd v, const double2*) { return v; }
+__device__ __forceinline__ cd rounded(cd v, const float2*) {
+    return cd{(double)(float)v.re, (double)(float)v.im};
+}
+
+// ---- interpolation prefactors (Sec. 3) ----------------------------------------------
+// f^l_j = 1 - j/n for l = 0 and j/n for l = 1.
+__device__ __forceinline__ double axis_weight(int j, int n, int l) {
+    double t = (double)j / (double)n;
+    return l ? t : 1.0 - t;
+}
+// trilinear f^{lmn}(sub) = f^l_{j1} f^m_{j2} f^n_{j3}, corner z = 4l + 2m + n;
+// neighbours == 1: one-hot on the nearest corner (j/n <= 1/2 picks l = 0 per axis).
+__device__ __forceinline__ double prefactor(int sub, int z, int n_div, int neighbours) {
+    int j3 = sub % n_div;
+    int j2 = (sub / n_div) % n_div;
+    int j1 = sub / (n_div * n_div);
+    int l = (z >> 2) & 1, m = (z >> 1) & 1, n = z & 1;
+    if (neighbours == 1) {
+        int l1 = (2 * j1 > n_div), m1 = (2 * j2 > n_div), n1 = (2 * j3 > n_div);
+        return (l == l1 && m == m1 && n == n1) ? 1.0 : 0.0;
+    }
+    return axis_weight(j1, n_div, l) * axis_weight(j2, n_div, m) * axis_weight(j3, n_div, n);
+}
+
+// coarse index of corner z of a cell (periodic wrap), Eq. (neighborhood)
+__device__ __forceinline__ int corner_index(int cell, int z, int n_c) {
+    int i3 = cell % n_c;
+    int i2 = (cell / n_c) % n_c;
+    int i1 = cell / (n_c * n_c);
+    i1 = (i1 + ((z >> 2) & 1)) % n_c;
+    i2 = (i2 + ((z >> 1) & 1)) % n_c;
+    i3 = (i3 + (z & 1)) % n_c;
+    return (i1 * n_c + i2) * n_c + i3;
+}
+// the cell whose corner z is coarse point k (inverse of corner_index)
+__device__ __forceinline__ int cell_of_corner(int k, int z, int n_c) {
+    int i3 = k % n_c;
+    int i2 = (k / n_c) % n_c;
+    int i1 = k / (n_c * n_c);
+    i1 = (i1 - ((z >> 2) & 1) + n_c) % n_c;
+    i2 = (i2 - ((z >> 1) & 1) + n_c) % n_c;
+    i3 = (i3 - (z & 1) + n_c) % n_c;
+    return (i1 * n_c + i2) * n_c + i3;
+}
+
+// ---- wavefront reductions -------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Block-wide sum of one double per thread in a fixed tree order.  `lds` must
+// hold blockDim.x / 64 doubles.  Result valid in every thread.
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+    v = wave_sum(v);
+    int wave = threadIdx.x / kWave;
+    int nw = blockDim.x / kWave;
+    __syncthreads();
+    if ((threadIdx.x % kWave) == 0) lds[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += lds[w];
+    __syncthreads();
+    return s;
+}
+
+// "last block" handshake: every block calls after writing its partials;
+// returns true in exactly one block (the last to arrive), which then sees every
+// other block's writes.  The counter is reset by that block.
+__device__ __forceinline__ bool last_block_arrival(unsigned int* counter, unsigned int n_blocks,
+                                                   int* lds_flag) {
+    __threadfence();  // each thread's partial writes are visible device-wide
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        int last = (prev == n_blocks - 1);
+        if (last) {
+            __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        *lds_flag = last;
+    }
+    __syncthreads();
+    bool last = *lds_flag != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+}  // namespace bse

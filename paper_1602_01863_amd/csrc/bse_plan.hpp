@@ -1,0 +1,92 @@
+// Host-side plan, workspace layout and launch interface of the BSE library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "bse_dg.h"
+
+namespace bse {
+
+constexpr int kMaxRhs = 4;
+constexpr int kMaxSplit = 64;        // column splits of the coarse product
+constexpr int kBlock = 256;          // threads of the reduction / product blocks
+
+// per-chain Lanczos state kept on the device between kernels.  The chain stores
+// unnormalised vectors u_j with psi_j = s_j u_j; the scales live here.
+struct ChainState {
+    double a;       // a_i of the current step
+    double s_cur;   // scale of the buffer holding psi_i (1 / b_i; 1 / ||P|| for i = 1)
+    double s_prev;  // scale of the buffer holding psi_{i-1}
+    double b_cur;   // b_i (0 for i = 1)
+    double ww;      // ||H psi_i - b_i psi_{i-1}||^2 of the current step
+    double pnorm2;  // ||P||^2
+    int32_t active;
+    int32_t steps;
+    int32_t status;
+    int32_t pad;
+};
+
+struct Geometry {
+    int n_c, n_div, ndiv3, ncells, nv, nc, np, ne, neighbours, dtype, n_orb_input;
+    int64_t nk, N, Nc;
+    int max_rhs;
+};
+
+bool make_geometry(const bse_dims* d, Geometry* g);
+
+// workspace regions (byte offsets from the workspace base)
+struct Layout {
+    size_t qpart, qbar, rvec, gpart, ppart, rpart, chain, gcount, pcount, rcount, vec_a, vec_b;
+    size_t total;
+};
+Layout make_layout(const Geometry& g);
+
+struct Plan {
+    Geometry g;
+    Layout L;
+    const void* Kc;
+    const void* d;
+    const double* delta;
+    char* ws;
+    int n_split;  // 0 = automatic
+    // timing of the coarse product
+    bool timing;
+    int ev_used;
+    double timed_ms;
+    int64_t timed_launches;
+    hipEvent_t* ev;
+    int ev_cap;
+};
+
+// launches implemented in hotpath.hip (return hipSuccess or the launch error)
+hipError_t launch_restrict(const Plan& p, int mode, const void* x, const void* w, const void* psi,
+                           const double* P, void* out, int step, double* a, double* b, int lda, int ldb,
+                           int n_rhs, hipStream_t s);
+hipError_t launch_collapse(const Plan& p, int n_rhs, bool scaled, hipStream_t s);
+hipError_t launch_gemv(Plan& p, int n_rhs, hipStream_t s);
+hipError_t launch_prolong(const Plan& p, int mode, const void* x, void* out_prev, int step,
+                          double* a, double* b, int lda, int ldb, int n_rhs, hipStream_t s);
+hipError_t launch_chain_report(const Plan& p, double* pnorm2, int32_t* steps, int32_t* status,
+                               int n_rhs, hipStream_t s);
+hipError_t launch_zero_counters(const Plan& p, hipStream_t s);
+bool supported_bands(int nv, int nc);
+
+// setup launches implemented in setup.hip
+hipError_t launch_overlaps(const Geometry& g, const double* vc, const double* vd, void* dout, hipStream_t s);
+hipError_t launch_transition_energies(const Geometry& g, const double* eps, double* out, hipStream_t s);
+hipError_t launch_coarse_kernel(const Geometry& g, const double* vecs, const double* tau,
+                                const bse_kernel_model& m, void* K, hipStream_t s);
+hipError_t launch_continued_fraction(const double* a, const double* b, int lda, int ldb, const double* pnorm2,
+                                     const int32_t* steps, int n_chains, double prefactor, const double* omega,
+                                     int n_omega, double eta, double* eps_re, double* eps_im, hipStream_t s);
+
+// modes of the restrict launch
+enum { RESTRICT_PLAIN = 0, RESTRICT_UPDATE = 1, RESTRICT_INIT = 2 };
+// modes of the prolong launch
+enum { PROLONG_PLAIN = 0, PROLONG_LANCZOS = 1 };
+
+void set_error(const char* fmt, ...);
+
+}  // namespace bse

@@ -1,0 +1,88 @@
+"""The C-ABI library loads and exports what include/bse_dg.h declares; host-side
+argument checks reject bad input before any device work (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bse_dg.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bse_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def bse():
+    from paper_1602_01863_amd import bse as mod
+    return mod
+
+
+def test_every_declared_symbol_is_exported(bse):
+    names = _declared()
+    assert len(names) >= 15
+    lib = bse.library()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(bse.EXPORTED) == names
+
+
+def test_version_and_sizes(bse):
+    assert "gfx950" in bse.bse_version()
+    d = bse.Dims(8, 4, 3, 6, 9, 3, bse.BSE_F32, 8)
+    assert bse.bse_coarse_kernel_bytes(d) == 9216 * 9216 * 8
+    assert bse.bse_overlaps_bytes(d) == 512 * 8 * 45 * 64 * 8
+    assert bse.bse_workspace_bytes(d) > 2 * 589824 * 3 * 8
+    d64 = bse.Dims(4, 2, 3, 3, 6, 1, bse.BSE_F64, 8)
+    assert bse.bse_coarse_kernel_bytes(d64) == 576 * 576 * 16
+
+
+@pytest.mark.parametrize("fields", [
+    dict(n_coarse=0), dict(n_div=0), dict(nv=0), dict(max_rhs=0), dict(max_rhs=5),
+    dict(dtype=7), dict(neighbours=4),
+])
+def test_invalid_dims_rejected(bse, fields):
+    base = dict(n_coarse=4, n_div=2, nv=3, nc=3, n_orb=6, max_rhs=1, dtype=0, neighbours=8)
+    base.update(fields)
+    d = bse.Dims(**base)
+    assert bse.bse_workspace_bytes(d) == 0
+    assert bse.library().bse_last_error().decode() != ""
+
+
+def test_plan_create_checks_before_device_work(bse):
+    lib = bse.library()
+    d = bse.Dims(4, 2, 3, 3, 6, 1, bse.BSE_F64, 8)
+    plan = ctypes.c_void_p()
+    # NULL inputs
+    st = lib.bse_plan_create(ctypes.byref(d), None, None, None, None, 0, None, ctypes.byref(plan))
+    assert st == bse.BSE_ERR_INVALID_ARG
+    # unsupported band counts
+    d2 = bse.Dims(4, 2, 5, 5, 10, 1, bse.BSE_F64, 8)
+    st = lib.bse_plan_create(ctypes.byref(d2), 1, 1, 1, 256, 1 << 30, None, ctypes.byref(plan))
+    assert st == bse.BSE_ERR_UNSUPPORTED
+    # misaligned or short workspace
+    st = lib.bse_plan_create(ctypes.byref(d), 1, 1, 1, 8, 1 << 30, None, ctypes.byref(plan))
+    assert st == bse.BSE_ERR_WORKSPACE
+    st = lib.bse_plan_create(ctypes.byref(d), 1, 1, 1, 256, 16, None, ctypes.byref(plan))
+    assert st == bse.BSE_ERR_WORKSPACE
+    assert not plan.value
+
+
+def test_other_entry_points_check_arguments(bse):
+    lib = bse.library()
+    assert lib.bse_interp_matvec(None, None, None, 1, None) == bse.BSE_ERR_INVALID_ARG
+    assert lib.bse_haydock_run(None, None, 1, 1, None, None, None, None, None, None) == bse.BSE_ERR_INVALID_ARG
+    assert lib.bse_continued_fraction(1, 1, 10, 5, 1, 1, 1, 1.0, 1, 1, 0.1, 1, 1, None) == bse.BSE_ERR_INVALID_ARG
+    assert lib.bse_continued_fraction(1, 1, 10, 11, 1, 1, 1, 1.0, 1, 1, 0.0, 1, 1, None) == bse.BSE_ERR_INVALID_ARG
+    d = bse.Dims(4, 2, 3, 3, 6, 1, bse.BSE_F64, 8)
+    m = bse.KernelModel(12.0, 0.3, 6.0, 9, 16)
+    assert lib.bse_build_coarse_kernel(ctypes.byref(d), 1, 1, ctypes.byref(m), 1, None) == bse.BSE_ERR_INVALID_ARG
+    d_big = bse.Dims(4, 2, 3, 6, 20, 1, bse.BSE_F64, 8)
+    m = bse.KernelModel(12.0, 0.3, 6.0, 4, 16)
+    assert lib.bse_build_coarse_kernel(ctypes.byref(d_big), 1, 1, ctypes.byref(m), 1, None) == bse.BSE_ERR_UNSUPPORTED
+    assert lib.bse_plan_set_gemv_splits(None, 4) == bse.BSE_ERR_INVALID_ARG
