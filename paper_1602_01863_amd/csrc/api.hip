@@ -94,11 +94,11 @@ Layout make_layout(const Geometry& g) {
     L.qbar = take((size_t)g.Nc * R * sizeof(double2));
     L.rvec = take((size_t)g.Nc * R * sizeof(double2));
     L.gpart = take((size_t)kMaxSplit * g.Nc * R * sizeof(double2));
-    L.ppart = take((size_t)g.ncells * R * 2 * sizeof(double));
+    L.ppart = take((size_t)g.ncells * R * 2 * 2 * sizeof(double));
     L.rpart = take((size_t)g.ncells * R * 2 * sizeof(double));
     L.chain = take((size_t)kMaxRhs * sizeof(ChainState));
     // counters, contiguous: one per row block of the product, then prolong, then restrict
-    const size_t nrowblk = (size_t)(g.Nc + 127) / 128;
+    const size_t nrowblk = (size_t)(g.Nc + kWave - 1) / kWave;   // product row blocks hold >= 64 rows
     L.gcount = take(nrowblk * sizeof(unsigned int));
     L.pcount = take(sizeof(unsigned int));
     L.rcount = take(sizeof(unsigned int));

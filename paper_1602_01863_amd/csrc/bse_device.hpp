@@ -62,10 +62,28 @@ __device__ __forceinline__ cd ld(const float2* p) {
 }
 __device__ __forceinline__ void st(double2* p, cd v) { *p = make_double2(v.re, v.im); }
 __device__ __forceinline__ void st(float2* p, cd v) { *p = make_float2((float)v.re, (float)v.im); }
+__device__ __forceinline__ cd cv(double2 v) { return cd{v.x, v.y}; }
+__device__ __forceinline__ cd cv(float2 v) { return cd{(double)v.x, (double)v.y}; }
 // value after a round trip through the storage type
 __device__ __forceinline__ cd rounded(cd v, const double2*) { return v; }
 __device__ __forceinline__ cd rounded(cd v, const float2*) {
     return cd{(double)(float)v.re, (double)(float)v.im};
+}
+
+// ---- buffer loads: per-lane 32-bit offset, uniform offset in a scalar register ----------
+// The resource covers `bytes` from `base`; loads past it return zero (hardware check).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <class T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ float2 bload<float2>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double2 bload<double2>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
 // ---- interpolation prefactors (Sec. 3) ----------------------------------------------

@@ -82,6 +82,17 @@ hipError_t launch_continued_fraction(const double* a, const double* b, int lda, 
                                      const int32_t* steps, int n_chains, double prefactor, const double* omega,
                                      int n_omega, double eta, double* eps_re, double* eps_im, hipStream_t s);
 
+// band pairs (nv, nc) compiled into the hot-path kernels
+#define BSE_BANDS(X) X(1, 1) X(1, 2) X(2, 2) X(2, 3) X(3, 3) X(3, 4) X(3, 6) X(4, 6)
+
+// per-precision, per-band launchers (restrict.hip, prolong.hip)
+template <class M2, class V2, int NV, int NC>
+hipError_t restrict_launch(const Plan& p, int mode, const void* x, const void* w, const void* psi, const double* P,
+                           void* out, int step, double* a, double* b, int lda, int ldb, int n_rhs, hipStream_t s);
+template <class M2, class V2, int NV, int NC>
+hipError_t prolong_launch(const Plan& p, int mode, const void* x, void* out, int step, double* a, int lda,
+                          int n_rhs, hipStream_t s);
+
 // modes of the restrict launch
 enum { RESTRICT_PLAIN = 0, RESTRICT_UPDATE = 1, RESTRICT_INIT = 2 };
 // modes of the prolong launch

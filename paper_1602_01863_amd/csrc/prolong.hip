@@ -1,0 +1,384 @@
+// Prolong (Eq. matmul3) plus the diagonal of Eq. (bse1):
+//
+//   w_k = delta_k (.) psi_k + sum_z f(k, z) Dv_z r_{k~z} Dc_z^H   [- b_i psi_{i-1} in a chain]
+//
+// One block per coarse cell; wavefront = right-hand side, lane = subpoint, so each
+// lane owns its output block and nothing is reduced across lanes.  In a chain the
+// block also forms FP64 partials of <u_i|w> and ||w||^2 and the last block turns
+// them into a_i (Eq. ai).
+//
+// Main form (n_div^3 <= 64): the block stages the overlaps of one corner at a time
+// in LDS with coalesced loads, double-buffered (the loads for corner z+1 are in
+// flight while corner z is computed), so every wavefront of the cell reads them from
+// LDS; the 8 coarse blocks r_{k~z} sit in LDS as well.  Two wavefronts per
+// right-hand side split the conduction index c in halves, which halves the FP64
+// accumulators each lane holds.
+
+#include <hip/hip_runtime.h>
+
+#include "bse_device.hpp"
+#include "bse_plan.hpp"
+
+namespace bse {
+
+// ---- general form: any number of subpoints per cell, overlaps read from global memory
+template <class M2, class V2, int NV, int NC, int MODE>
+__global__ __launch_bounds__(256) void k_prolong1(const M2* __restrict__ d, const double* __restrict__ delta,
+                                                 const double2* __restrict__ rvec, const V2* __restrict__ x,
+                                                 V2* __restrict__ out, double* __restrict__ ppart,
+                                                 unsigned int* __restrict__ pcount, ChainState* __restrict__ chain,
+                                                 double* __restrict__ alpha, int lda, int step, int n_c, int n_div,
+                                                 int neighbours, int64_t N, int n_rhs) {
+    constexpr int NP = NV * NC;
+    constexpr int NE = NV * NV + NC * NC;
+    __shared__ double red[kBlock / kWave];
+    __shared__ int flag;
+    const int ndiv3 = n_div * n_div * n_div;
+    const int rhs = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int lane = threadIdx.x % kWave;
+    const int cell = blockIdx.x;
+    const int64_t kd0 = (int64_t)cell * ndiv3;
+    double s_cur = 1.0, c_prev = 0.0;
+    if (MODE == PROLONG_LANCZOS) {
+        s_cur = chain[rhs].s_cur;                         // psi_i = s_i u_i
+        c_prev = chain[rhs].b_cur * chain[rhs].s_prev;    // b_i psi_{i-1} = b_i s_{i-1} u_{i-1}
+    }
+    const bool use_prev = (MODE == PROLONG_LANCZOS) && c_prev != 0.0;
+    double pw = 0.0, ww = 0.0;
+
+    for (int sub = lane; sub < ndiv3; sub += kWave) {
+        const int64_t kd = kd0 + sub;
+        const int64_t t0 = (int64_t)rhs * N + kd * NP;
+        cd acc[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const cd xv = ld(x + t0 + p);
+            acc[p] = cscale(xv, delta[kd * NP + p] * s_cur);
+            if (use_prev) {
+                const cd pv = ld(out + t0 + p);
+                acc[p].re = fma(-c_prev, pv.re, acc[p].re);
+                acc[p].im = fma(-c_prev, pv.im, acc[p].im);
+            }
+        }
+        for (int z = 0; z < 8; ++z) {
+            const double f = prefactor(sub, z, n_div, neighbours);
+            const int k = corner_index(cell, z, n_c);
+            const double2* rb = rvec + (int64_t)k * NP * n_rhs + rhs;
+            const M2* db = d + ((int64_t)(cell * 8 + z) * NE) * ndiv3 + sub;
+            cd dv[NV * NV];
+#pragma unroll
+            for (int e = 0; e < NV * NV; ++e) dv[e] = cscale(ld(db + (int64_t)e * ndiv3), f);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                // t[n1] = sum_{n2} r[n1][n2] conj(Dc[c][n2])
+                cd t[NV];
+#pragma unroll
+                for (int n1 = 0; n1 < NV; ++n1) t[n1] = cmake(0.0, 0.0);
+#pragma unroll
+                for (int n2 = 0; n2 < NC; ++n2) {
+                    const cd dc = ld(db + (int64_t)(NV * NV + c * NC + n2) * ndiv3);
+#pragma unroll
+                    for (int n1 = 0; n1 < NV; ++n1) {
+                        const double2 r = rb[(int64_t)(n1 * NC + n2) * n_rhs];
+                        cfma_jc(t[n1], cmake(r.x, r.y), dc);
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int n1 = 0; n1 < NV; ++n1) cfma(acc[v * NC + c], dv[v * NV + n1], t[n1]);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            st(out + t0 + p, acc[p]);
+            if (MODE == PROLONG_LANCZOS) {
+                const cd w = rounded(acc[p], out);
+                const cd xv = ld(x + t0 + p);
+                pw = fma(xv.re, w.re, pw);
+                pw = fma(xv.im, w.im, pw);
+                ww = fma(w.re, w.re, ww);
+                ww = fma(w.im, w.im, ww);
+            }
+        }
+    }
+    if (MODE != PROLONG_LANCZOS) return;
+
+    pw = wave_sum(pw);
+    ww = wave_sum(ww);
+    if (lane == 0) {
+        ppart[((int64_t)cell * n_rhs + rhs) * 2] = pw;
+        ppart[((int64_t)cell * n_rhs + rhs) * 2 + 1] = ww;
+    }
+    const int ncells = gridDim.x;
+    if (!last_block_arrival(pcount, (unsigned)ncells, &flag)) return;
+    for (int r = 0; r < n_rhs; ++r) {
+        double s2[2];
+        for (int comp = 0; comp < 2; ++comp) {
+            double v = 0.0;
+            for (int c = threadIdx.x; c < ncells; c += blockDim.x) v += ppart[((int64_t)c * n_rhs + r) * 2 + comp];
+            s2[comp] = block_sum(v, red);
+        }
+        if (threadIdx.x != 0) continue;
+        ChainState st = chain[r];
+        st.a = 0.0;
+        st.ww = 0.0;
+        if (st.active) {
+            const double a = st.s_cur * s2[0];   // a_i = Re <psi_i | w>  (Eq. ai)
+            if (!isfinite(a) || !isfinite(s2[1])) {
+                st.status = BSE_ERR_NONFINITE;
+                st.active = 0;
+                st.s_cur = 0.0;
+            } else {
+                alpha[(int64_t)r * lda + step] = a;
+                st.a = a;
+                st.ww = s2[1];
+                st.steps = step + 1;
+            }
+        }
+        chain[r] = st;
+    }
+}
+
+
+// ---- main form: overlaps staged per corner in LDS ------------------------------------
+constexpr int kProlongBlock = 512;   // 4 right-hand sides x 2 halves
+
+template <class M2, class V2, int NV, int NC, int MODE>
+__global__ __launch_bounds__(512, 2) void k_prolong2(const M2* __restrict__ d, const double* __restrict__ delta,
+                                                  const double2* __restrict__ rvec, const V2* __restrict__ x,
+                                                  V2* __restrict__ out, double* __restrict__ ppart,
+                                                  unsigned int* __restrict__ pcount, ChainState* __restrict__ chain,
+                                                  double* __restrict__ alpha, int lda, int step, int n_c, int n_div,
+                                                  int neighbours, int64_t N, int n_rhs) {
+    constexpr int NP = NV * NC;
+    constexpr int NE = NV * NV + NC * NC;
+    constexpr int NCH = (NC + 1) / 2;
+    constexpr int PF = (NE * kWave + kProlongBlock - 1) / kProlongBlock;  // staged elements per thread
+    extern __shared__ double2 lds2[];
+    __shared__ double red[kProlongBlock / kWave];
+    __shared__ int flag;
+    const int ndiv3 = n_div * n_div * n_div;
+    const int blk = NE * ndiv3;
+    M2* dbuf0 = reinterpret_cast<M2*>(lds2);
+    M2* dbuf1 = dbuf0 + blk;
+    double2* rs = lds2 + (2 * blk * (int)sizeof(M2) + 15) / 16;
+    const int cell = blockIdx.x;
+    const int t = threadIdx.x;
+    const int wave = t / kWave;
+    const int lane = t % kWave;
+    const int rhs = wave >> 1;
+    const int h = wave & 1;
+    const bool wave_on = rhs < n_rhs;
+    const bool active = wave_on && lane < ndiv3;
+
+    // coarse blocks r_{k~z} of the 8 corners: rs[z][p][r]
+    const int per = NP * n_rhs;
+    for (int i = t; i < 8 * per; i += blockDim.x) {
+        const int zz = i / per;
+        rs[i] = rvec[(int64_t)corner_index(cell, zz, n_c) * per + (i - zz * per)];
+    }
+    const M2* dcell = d + (int64_t)cell * 8 * blk;
+    for (int i = t; i < blk; i += blockDim.x) dbuf0[i] = dcell[i];
+
+    double s_cur = 1.0, c_prev = 0.0;
+    if (MODE == PROLONG_LANCZOS && wave_on) {
+        s_cur = chain[rhs].s_cur;                         // psi_i = s_i u_i
+        c_prev = chain[rhs].b_cur * chain[rhs].s_prev;    // b_i psi_{i-1} = b_i s_{i-1} u_{i-1}
+    }
+    const int64_t kd = (int64_t)cell * ndiv3 + lane;
+    const int64_t t0 = (int64_t)rhs * N + kd * NP;
+    cd acc[NV][NCH];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) {
+            acc[v][q] = cmake(0.0, 0.0);
+            const int c = h * NCH + q;
+            if (active && c < NC) {
+                const int p = v * NC + c;
+                const cd xv = ld(x + t0 + p);
+                acc[v][q] = cscale(xv, delta[kd * NP + p] * s_cur);
+                if (MODE == PROLONG_LANCZOS && c_prev != 0.0) {
+                    const cd pv = ld(out + t0 + p);
+                    acc[v][q].re = fma(-c_prev, pv.re, acc[v][q].re);
+                    acc[v][q].im = fma(-c_prev, pv.im, acc[v][q].im);
+                }
+            }
+        }
+
+    for (int z = 0; z < 8; ++z) {
+        M2 pf[PF];
+        if (z < 7) {
+            const M2* dn = dcell + (int64_t)(z + 1) * blk;
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int i = t + q * kProlongBlock;
+                if (i < blk) pf[q] = dn[i];
+            }
+        }
+        __syncthreads();
+        const M2* cur = (z & 1) ? dbuf1 : dbuf0;
+        if (active) {
+            const double f = prefactor(lane, z, n_div, neighbours);
+            const double2* rz = rs + z * per + rhs;
+            M2 dv[NV * NV];   // storage precision, widened at use
+#pragma unroll
+            for (int e = 0; e < NV * NV; ++e) dv[e] = cur[e * ndiv3 + lane];
+            // tt[q][n1] = sum_{n2} r[n1][n2] conj(Dc[c(q)][n2]), one column of r at a time
+            cd tt[NCH][NV];
+#pragma unroll
+            for (int q = 0; q < NCH; ++q)
+#pragma unroll
+                for (int n1 = 0; n1 < NV; ++n1) tt[q][n1] = cmake(0.0, 0.0);
+#pragma unroll
+            for (int n2 = 0; n2 < NC; ++n2) {
+                __builtin_amdgcn_sched_barrier(0);
+                cd rc[NV];
+#pragma unroll
+                for (int n1 = 0; n1 < NV; ++n1) {
+                    const double2 r = rz[(n1 * NC + n2) * n_rhs];
+                    rc[n1] = cmake(r.x, r.y);
+                }
+#pragma unroll
+                for (int q = 0; q < NCH; ++q) {
+                    const int c = h * NCH + q;
+                    if (c >= NC) break;
+                    const cd dc = cv(cur[(NV * NV + c * NC + n2) * ndiv3 + lane]);
+#pragma unroll
+                    for (int n1 = 0; n1 < NV; ++n1) cfma_jc(tt[q][n1], rc[n1], dc);
+                }
+            }
+            // acc[v][q] += f sum_{n1} Dv[v][n1] tt[q][n1]
+#pragma unroll
+            for (int q = 0; q < NCH; ++q)
+#pragma unroll
+                for (int n1 = 0; n1 < NV; ++n1) tt[q][n1] = cscale(tt[q][n1], f);
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int n1 = 0; n1 < NV; ++n1) {
+                    const cd dvv = cv(dv[v * NV + n1]);
+#pragma unroll
+                    for (int q = 0; q < NCH; ++q) cfma(acc[v][q], dvv, tt[q][n1]);
+                }
+        }
+        if (z < 7) {
+            M2* nxt = (z & 1) ? dbuf0 : dbuf1;
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int i = t + q * kProlongBlock;
+                if (i < blk) nxt[i] = pf[q];
+            }
+        }
+    }
+
+    double pw = 0.0, ww = 0.0;
+    if (active) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int q = 0; q < NCH; ++q) {
+                const int c = h * NCH + q;
+                if (c >= NC) continue;
+                const int p = v * NC + c;
+                st(out + t0 + p, acc[v][q]);
+                if (MODE == PROLONG_LANCZOS) {
+                    const cd w = rounded(acc[v][q], out);
+                    const cd xv = ld(x + t0 + p);
+                    pw = fma(xv.re, w.re, pw);
+                    pw = fma(xv.im, w.im, pw);
+                    ww = fma(w.re, w.re, ww);
+                    ww = fma(w.im, w.im, ww);
+                }
+            }
+    }
+    if (MODE != PROLONG_LANCZOS) return;
+
+    pw = wave_sum(pw);
+    ww = wave_sum(ww);
+    if (wave_on && lane == 0) {
+        double* q = ppart + (((int64_t)cell * n_rhs + rhs) * 2 + h) * 2;
+        q[0] = pw;
+        q[1] = ww;
+    }
+    const int ncells = gridDim.x;
+    if (!last_block_arrival(pcount, (unsigned)ncells, &flag)) return;
+    for (int r = 0; r < n_rhs; ++r) {
+        double s2[2];
+        for (int comp = 0; comp < 2; ++comp) {
+            double v = 0.0;
+            for (int c = t; c < ncells; c += blockDim.x) {
+                const double* q = ppart + ((int64_t)c * n_rhs + r) * 4;
+                v += q[comp] + q[2 + comp];
+            }
+            s2[comp] = block_sum(v, red);
+        }
+        if (t != 0) continue;
+        ChainState stt = chain[r];
+        stt.a = 0.0;
+        stt.ww = 0.0;
+        if (stt.active) {
+            const double a = stt.s_cur * s2[0];   // a_i = Re <psi_i | w>  (Eq. ai)
+            if (!isfinite(a) || !isfinite(s2[1])) {
+                stt.status = BSE_ERR_NONFINITE;
+                stt.active = 0;
+                stt.s_cur = 0.0;
+            } else {
+                alpha[(int64_t)r * lda + step] = a;
+                stt.a = a;
+                stt.ww = s2[1];
+                stt.steps = step + 1;
+            }
+        }
+        chain[r] = stt;
+    }
+}
+
+static size_t prolong2_lds(int ne, int ndiv3, int np, int n_rhs, size_t melem) {
+    return (2 * (size_t)ne * ndiv3 * melem + 15) / 16 * 16 + (size_t)8 * np * n_rhs * sizeof(double2);
+}
+
+template <class M2, class V2, int NV, int NC>
+hipError_t prolong_launch(const Plan& p, int mode, const void* x, void* out, int step, double* a, int lda,
+                          int n_rhs, hipStream_t s) {
+    const Geometry& g = p.g;
+    const double2* rvec = reinterpret_cast<const double2*>(p.ws + p.L.rvec);
+    double* ppart = reinterpret_cast<double*>(p.ws + p.L.ppart);
+    unsigned int* pcount = reinterpret_cast<unsigned int*>(p.ws + p.L.pcount);
+    ChainState* chain = reinterpret_cast<ChainState*>(p.ws + p.L.chain);
+    const M2* d = reinterpret_cast<const M2*>(p.d);
+    const V2* xv = reinterpret_cast<const V2*>(x);
+    V2* ov = reinterpret_cast<V2*>(out);
+    constexpr int NP = NV * NC, NE = NV * NV + NC * NC;
+    const size_t lds = prolong2_lds(NE, g.ndiv3, NP, n_rhs, sizeof(M2));
+    if (g.ndiv3 <= kWave && lds <= 64 * 1024) {
+        dim3 grid(g.ncells), block(kProlongBlock);
+        if (mode == PROLONG_PLAIN)
+            hipLaunchKernelGGL((k_prolong2<M2, V2, NV, NC, PROLONG_PLAIN>), grid, block, lds, s, d, p.delta, rvec, xv,
+                               ov, ppart, pcount, chain, nullptr, 0, 0, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
+        else
+            hipLaunchKernelGGL((k_prolong2<M2, V2, NV, NC, PROLONG_LANCZOS>), grid, block, lds, s, d, p.delta, rvec,
+                               xv, ov, ppart, pcount, chain, a, lda, step, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
+    } else {
+        dim3 grid(g.ncells), block(kWave * n_rhs);
+        if (mode == PROLONG_PLAIN)
+            hipLaunchKernelGGL((k_prolong1<M2, V2, NV, NC, PROLONG_PLAIN>), grid, block, 0, s, d, p.delta, rvec, xv,
+                               ov, ppart, pcount, chain, nullptr, 0, 0, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
+        else
+            hipLaunchKernelGGL((k_prolong1<M2, V2, NV, NC, PROLONG_LANCZOS>), grid, block, 0, s, d, p.delta, rvec,
+                               xv, ov, ppart, pcount, chain, a, lda, step, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
+    }
+    return hipGetLastError();
+}
+
+#define BSE_PROLONG_INST(M2, V2, A, B)                                                                             \
+    template hipError_t prolong_launch<M2, V2, A, B>(const Plan&, int, const void*, void*, int, double*, int, int, \
+                                                     hipStream_t);
+#define BSE_PROLONG_ALL(A, B)                 \
+    BSE_PROLONG_INST(double2, double2, A, B)  \
+    BSE_PROLONG_INST(float2, float2, A, B)    \
+    BSE_PROLONG_INST(float2, double2, A, B)
+BSE_BANDS(BSE_PROLONG_ALL)
+
+}  // namespace bse
