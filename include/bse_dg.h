@@ -151,9 +151,9 @@ bse_status bse_build_coarse_kernel(const bse_dims* dims, const double* vecs_coar
  *   d          device, overlaps in the layout of bse_build_overlaps
  *   delta      device FP64 [N]
  *   workspace  device, >= bse_workspace_bytes(dims) bytes, 256-byte aligned; owned
- *              by the plan until bse_plan_destroy; one plan must not run on two
- *              streams at once.
- * Zeroes the workspace counters on `stream`.
+ *              by the plan until bse_plan_destroy; its contents need no
+ *              initialisation; one plan must not run on two streams at once.
+ *   stream     reserved (nothing is enqueued).
  */
 bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d,
                            const double* delta, void* workspace, size_t workspace_bytes,
@@ -203,7 +203,8 @@ bse_status bse_continued_fraction(const double* a, const double* b, int32_t lda,
                                   hipStream_t stream);
 
 /* Kernel timing: when enabled, the plan records HIP events around every launch
- * of the coarse product (the dominant kernel) on the stream it is launched on.
+ * of the coarse product (the dominant kernel: the split product and the kernel
+ * that adds its splits) on the stream it is launched on.
  * bse_plan_get_timing synchronises those events and returns the total time in
  * milliseconds and the number of timed launches since the last reset. */
 bse_status bse_plan_set_timing(bse_plan* plan, int32_t enable);

@@ -96,19 +96,13 @@ Layout make_layout(const Geometry& g) {
     L.gpart = take((size_t)kMaxSplit * g.Nc * R * sizeof(double2));
     L.ppart = take((size_t)g.ncells * R * 2 * 2 * sizeof(double));
     L.rpart = take((size_t)g.ncells * R * 2 * sizeof(double));
-    L.chain = take((size_t)kMaxRhs * sizeof(ChainState));
-    // counters, contiguous: one per row block of the product, then prolong, then restrict
-    const size_t nrowblk = (size_t)(g.Nc + kWave - 1) / kWave;   // product row blocks hold >= 64 rows
-    L.gcount = take(nrowblk * sizeof(unsigned int));
-    L.pcount = take(sizeof(unsigned int));
-    L.rcount = take(sizeof(unsigned int));
+    L.chain = take((size_t)2 * kMaxRhs * sizeof(ChainState));
+    L.pend = take((size_t)kMaxRhs * sizeof(StepScalars));
     L.vec_a = take((size_t)g.N * R * vec_elem_bytes(g.dtype));
     L.vec_b = take((size_t)g.N * R * vec_elem_bytes(g.dtype));
     L.total = off;
     return L;
 }
-
-hipError_t launch_zero_counters(const Plan& p, hipStream_t s);
 
 // ---- continued fraction (Eq. fraccont) ------------------------------------------------
 __global__ __launch_bounds__(256) void k_continued_fraction(const double* __restrict__ a, const double* __restrict__ b,
@@ -274,11 +268,7 @@ bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d, 
     p->ev_used = 0;
     p->timed_ms = 0.0;
     p->timed_launches = 0;
-    hipError_t e = launch_zero_counters(*p, stream);
-    if (e != hipSuccess) {
-        delete p;
-        return hip_fail(e, "bse_plan_create");
-    }
+    (void)stream;
     *plan_out = reinterpret_cast<bse_plan*>(p);
     return BSE_OK;
 }
@@ -316,9 +306,9 @@ bse_status bse_interp_matvec(bse_plan* plan, const void* x, void* y, int32_t n_r
     }
     hipError_t e = launch_restrict(p, RESTRICT_PLAIN, x, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr,
                                    0, 0, n_rhs, stream);
-    if (e == hipSuccess) e = launch_collapse(p, n_rhs, false, stream);
+    if (e == hipSuccess) e = launch_collapse(p, COLLAPSE_PLAIN, 0, nullptr, 0, n_rhs, stream);
     if (e == hipSuccess) e = launch_gemv(p, n_rhs, stream);
-    if (e == hipSuccess) e = launch_prolong(p, PROLONG_PLAIN, x, y, 0, nullptr, nullptr, 0, 0, n_rhs, stream);
+    if (e == hipSuccess) e = launch_prolong(p, PROLONG_PLAIN, x, y, 0, n_rhs, stream);
     return e == hipSuccess ? BSE_OK : hip_fail(e, "bse_interp_matvec");
 }
 
@@ -336,19 +326,19 @@ bse_status bse_haydock_run(bse_plan* plan, const double* P, int32_t n_rhs, int32
     const int lda = n_steps, ldb = n_steps + 1;
     void* A = p.ws + p.L.vec_a;  // u_{i-1}, then w, then u_{i+1}
     void* B = p.ws + p.L.vec_b;  // u_i
-    // u_1 = P, ||P||, coarse vector of psi_1; zero-fills a and b
+    // u_1 = P, ||u_1||, ||P||, coarse vector of psi_1; zero-fills a and b
     hipError_t e = launch_restrict(p, RESTRICT_INIT, nullptr, nullptr, nullptr, P, B, 0, a, b, lda, ldb, n_rhs,
                                    stream);
-    if (e == hipSuccess) e = launch_collapse(p, n_rhs, true, stream);
+    if (e == hipSuccess) e = launch_collapse(p, COLLAPSE_INIT, 0, b, ldb, n_rhs, stream);
     for (int i = 0; i < n_steps && e == hipSuccess; ++i) {
         e = launch_gemv(p, n_rhs, stream);
-        if (e == hipSuccess) e = launch_prolong(p, PROLONG_LANCZOS, B, A, i, a, b, lda, ldb, n_rhs, stream);
+        if (e == hipSuccess) e = launch_prolong(p, PROLONG_LANCZOS, B, A, i, n_rhs, stream);
         if (e == hipSuccess)
             e = launch_restrict(p, RESTRICT_UPDATE, nullptr, A, B, nullptr, A, i, a, b, lda, ldb, n_rhs, stream);
-        if (e == hipSuccess && i + 1 < n_steps) e = launch_collapse(p, n_rhs, true, stream);
+        if (e == hipSuccess) e = launch_collapse(p, COLLAPSE_STEP, i, b, ldb, n_rhs, stream);
         std::swap(A, B);
     }
-    if (e == hipSuccess) e = launch_chain_report(p, pnorm2, steps_done, status, n_rhs, stream);
+    if (e == hipSuccess) e = launch_chain_report(p, n_steps, pnorm2, steps_done, status, n_rhs, stream);
     return e == hipSuccess ? BSE_OK : hip_fail(e, "bse_haydock_run");
 }
 

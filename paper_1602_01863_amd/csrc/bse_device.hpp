@@ -149,26 +149,13 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
     return s;
 }
 
-// "last block" handshake: every block calls after writing its partials;
-// returns true in exactly one block (the last to arrive), which then sees every
-// other block's writes.  The counter is reset by that block.
-__device__ __forceinline__ bool last_block_arrival(unsigned int* counter, unsigned int n_blocks,
-                                                   int* lds_flag) {
-    __threadfence();  // each thread's partial writes are visible device-wide
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-        int last = (prev == n_blocks - 1);
-        if (last) {
-            __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        *lds_flag = last;
-    }
-    __syncthreads();
-    bool last = *lds_flag != 0;
-    if (last) __threadfence();
-    return last;
+// Sum of n doubles at p[i * stride] (i < n) by the whole block, in an order that
+// depends only on n and blockDim: every block that calls it on the same data gets
+// the same bits.  `lds` holds blockDim.x / 64 doubles.
+__device__ __forceinline__ double block_sum_strided(const double* p, int n, int stride, double* lds) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[(int64_t)i * stride];
+    return block_sum(v, lds);
 }
 
 }  // namespace bse

@@ -13,19 +13,28 @@ constexpr int kMaxRhs = 4;
 constexpr int kMaxSplit = 64;        // column splits of the coarse product
 constexpr int kBlock = 256;          // threads of the reduction / product blocks
 
-// per-chain Lanczos state kept on the device between kernels.  The chain stores
-// unnormalised vectors u_j with psi_j = s_j u_j; the scales live here.
+// Per-chain Lanczos state kept on the device between kernels.  The chain stores
+// unnormalised vectors u_j with psi_j = s_j u_j; the scales live here.  Two copies
+// alternate between steps: the kernels of step i read copy i % 2 and the last kernel
+// of the step (the collapse) writes copy (i + 1) % 2, so no kernel reads a field that
+// another block of the same kernel writes.
 struct ChainState {
-    double a;       // a_i of the current step
-    double s_cur;   // scale of the buffer holding psi_i (1 / b_i; 1 / ||P|| for i = 1)
+    double s_cur;   // scale of the buffer holding psi_i (1 / b_i; 1 / ||u_1|| for i = 1)
     double s_prev;  // scale of the buffer holding psi_{i-1}
     double b_cur;   // b_i (0 for i = 1)
-    double ww;      // ||H psi_i - b_i psi_{i-1}||^2 of the current step
     double pnorm2;  // ||P||^2
     int32_t active;
     int32_t steps;
     int32_t status;
     int32_t pad;
+};
+
+// a_i and ||w||^2 of the current step, recorded by the restrict for the collapse
+struct StepScalars {
+    double a;
+    double ww;
+    int32_t ok;   // chain active and both values finite
+    int32_t pad[3];
 };
 
 struct Geometry {
@@ -38,7 +47,7 @@ bool make_geometry(const bse_dims* d, Geometry* g);
 
 // workspace regions (byte offsets from the workspace base)
 struct Layout {
-    size_t qpart, qbar, rvec, gpart, ppart, rpart, chain, gcount, pcount, rcount, vec_a, vec_b;
+    size_t qpart, qbar, rvec, gpart, ppart, rpart, chain, pend, vec_a, vec_b;
     size_t total;
 };
 Layout make_layout(const Geometry& g);
@@ -64,13 +73,12 @@ struct Plan {
 hipError_t launch_restrict(const Plan& p, int mode, const void* x, const void* w, const void* psi,
                            const double* P, void* out, int step, double* a, double* b, int lda, int ldb,
                            int n_rhs, hipStream_t s);
-hipError_t launch_collapse(const Plan& p, int n_rhs, bool scaled, hipStream_t s);
+hipError_t launch_collapse(const Plan& p, int mode, int step, double* b, int ldb, int n_rhs, hipStream_t s);
 hipError_t launch_gemv(Plan& p, int n_rhs, hipStream_t s);
-hipError_t launch_prolong(const Plan& p, int mode, const void* x, void* out_prev, int step,
-                          double* a, double* b, int lda, int ldb, int n_rhs, hipStream_t s);
-hipError_t launch_chain_report(const Plan& p, double* pnorm2, int32_t* steps, int32_t* status,
+hipError_t launch_prolong(const Plan& p, int mode, const void* x, void* out_prev, int step, int n_rhs,
+                          hipStream_t s);
+hipError_t launch_chain_report(const Plan& p, int n_steps, double* pnorm2, int32_t* steps, int32_t* status,
                                int n_rhs, hipStream_t s);
-hipError_t launch_zero_counters(const Plan& p, hipStream_t s);
 bool supported_bands(int nv, int nc);
 
 // setup launches implemented in setup.hip
@@ -90,11 +98,18 @@ template <class M2, class V2, int NV, int NC>
 hipError_t restrict_launch(const Plan& p, int mode, const void* x, const void* w, const void* psi, const double* P,
                            void* out, int step, double* a, double* b, int lda, int ldb, int n_rhs, hipStream_t s);
 template <class M2, class V2, int NV, int NC>
-hipError_t prolong_launch(const Plan& p, int mode, const void* x, void* out, int step, double* a, int lda,
-                          int n_rhs, hipStream_t s);
+hipError_t prolong_launch(const Plan& p, int mode, const void* x, void* out, int step, int n_rhs, hipStream_t s);
+
+// chain-state copy read by the kernels of a step, written by its collapse
+__host__ __device__ inline int state_in(int step) { return step & 1; }
+__host__ __device__ inline int state_out(int step) { return (step + 1) & 1; }
+// breakdown threshold: b_{i+1} <= tol ||w||, by vector storage precision
+inline double breakdown_tol(int dtype) { return dtype == BSE_F32 ? 1e-6 : 1e-12; }
 
 // modes of the restrict launch
 enum { RESTRICT_PLAIN = 0, RESTRICT_UPDATE = 1, RESTRICT_INIT = 2 };
+// modes of the collapse launch
+enum { COLLAPSE_PLAIN = 0, COLLAPSE_INIT = 1, COLLAPSE_STEP = 2 };
 // modes of the prolong launch
 enum { PROLONG_PLAIN = 0, PROLONG_LANCZOS = 1 };
 

@@ -10,8 +10,8 @@
 //
 // Grid: row blocks x column splits.  A block = 4 wavefronts on the same rows and
 // interleaved columns of one column chunk; qbar for the chunk sits in LDS.  The 4
-// wavefront partials are added in LDS in a fixed order, every block writes its split
-// partial, and the last block of each row block adds the splits in a fixed order.
+// wavefront partials are added in LDS in a fixed order and every block writes its
+// split partial; k_gemv_reduce then adds the splits of each output in a fixed order.
 
 #include <hip/hip_runtime.h>
 
@@ -99,13 +99,10 @@ __device__ __forceinline__ void gemv_stream(const M2* __restrict__ kp, const dou
 
 template <class M2, int NRHS, bool VEC>
 __global__ __launch_bounds__(256, 4) void k_gemv2(const M2* __restrict__ K, const double2* __restrict__ qbar,
-                                                  double2* __restrict__ part, double2* __restrict__ rout,
-                                                  unsigned int* __restrict__ counters, int Nc, int col_chunk,
-                                                  int n_split, int n_rowblk) {
+                                                  double2* __restrict__ part, int Nc, int col_chunk, int n_rowblk) {
     constexpr int E = Gv<M2>::E;
     constexpr int RW = kWave * E;
     extern __shared__ double2 smem[];
-    __shared__ int flag;
     const int rb = blockIdx.x % n_rowblk;
     const int s = blockIdx.x / n_rowblk;
     const int wave = threadIdx.x / kWave;
@@ -162,19 +159,20 @@ __global__ __launch_bounds__(256, 4) void k_gemv2(const M2* __restrict__ K, cons
                     part[((int64_t)s * Nc + row + e) * NRHS + r] = make_double2(acc[e][r].re, acc[e][r].im);
     }
 
-    if (last_block_arrival(counters + rb, (unsigned)n_split, &flag)) {
-        const int rbase = rb * RW;
-        const int nrow = min(RW, Nc - rbase);
-        for (int o = threadIdx.x; o < nrow * NRHS; o += blockDim.x) {
-            double re = 0.0, im = 0.0;
-            for (int t = 0; t < n_split; ++t) {
-                const double2 v = part[((int64_t)t * Nc + rbase) * NRHS + o];
-                re += v.x;
-                im += v.y;
-            }
-            rout[(int64_t)rbase * NRHS + o] = make_double2(re, im);
-        }
+}
+
+// r[o] = sum over the splits of part[split][o], o = row * NRHS + rhs, fixed order
+__global__ __launch_bounds__(256) void k_gemv_reduce(const double2* __restrict__ part, double2* __restrict__ rout,
+                                                     int64_t n_out, int n_split) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n_out) return;
+    double re = 0.0, im = 0.0;
+    for (int t = 0; t < n_split; ++t) {
+        const double2 v = part[(int64_t)t * n_out + o];
+        re += v.x;
+        im += v.y;
     }
+    rout[o] = make_double2(re, im);
 }
 
 static void gemv_shape(const Plan& p, int rw, int* n_rowblk, int* n_split, int* col_chunk) {
@@ -202,14 +200,16 @@ static hipError_t gemv_t(Plan& p, hipStream_t s) {
     const double2* qbar = reinterpret_cast<const double2*>(p.ws + p.L.qbar);
     double2* part = reinterpret_cast<double2*>(p.ws + p.L.gpart);
     double2* rvec = reinterpret_cast<double2*>(p.ws + p.L.rvec);
-    unsigned int* cnt = reinterpret_cast<unsigned int*>(p.ws + p.L.gcount);
     dim3 grid(n_rowblk * n_split), block(kBlock);
     if (vec)
-        hipLaunchKernelGGL((k_gemv2<M2, NRHS, true>), grid, block, lds, s, K, qbar, part, rvec, cnt, (int)g.Nc,
-                           chunk, n_split, n_rowblk);
+        hipLaunchKernelGGL((k_gemv2<M2, NRHS, true>), grid, block, lds, s, K, qbar, part, (int)g.Nc, chunk, n_rowblk);
     else
-        hipLaunchKernelGGL((k_gemv2<M2, NRHS, false>), grid, block, lds, s, K, qbar, part, rvec, cnt, (int)g.Nc,
-                           chunk, n_split, n_rowblk);
+        hipLaunchKernelGGL((k_gemv2<M2, NRHS, false>), grid, block, lds, s, K, qbar, part, (int)g.Nc, chunk, n_rowblk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n_out = g.Nc * NRHS;
+    hipLaunchKernelGGL(k_gemv_reduce, dim3((unsigned)((n_out + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, part, rvec,
+                       n_out, n_split);
     return hipGetLastError();
 }
 

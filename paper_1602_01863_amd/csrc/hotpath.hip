@@ -4,15 +4,18 @@
 // chain keeps unnormalised vectors u_j, psi_j = s_j u_j, with the scales in a
 // small device-side state, so that b_{i+1} is the norm of the vector actually
 // formed without an extra pass over memory:
-//   k_gemv2     r = K_c qbar           (gemv.hip; Eq. matmul2, corner sum collapsed)
+//   k_gemv2     r = K_c qbar by column splits, k_gemv_reduce adds the splits
+//               (gemv.hip; Eq. matmul2, corner sum collapsed)
 //   k_prolong2  w = delta psi_i + C^H r - b_i psi_{i-1} and a_i   (prolong.hip;
 //               Eq. matmul3, Eq. bse1 diagonal, Eq. ai)
 //   k_restrict2 u_{i+1} = w - a_i psi_i, b_{i+1} = ||u_{i+1}||, then the
 //               per-(cell, corner) coarse vectors of u_{i+1}  (restrict.hip;
 //               Eqs. bi, ci, matmul1)
 //   k_collapse  qbar(k~) = s_{i+1} x sum of the 8 (cell, corner) vectors on k~
-// This file holds the collapse, the chain report, counter reset and the dispatch
-// on band counts and storage precision.  Every sum is FP64; reductions use fixed
+// No kernel waits on another block: each kernel leaves per-block partials that the
+// next kernel in the stream adds in a fixed order.  This file holds the collapse
+// (which closes a chain step), the chain report and the dispatch on band counts and
+// storage precision.  Every sum is FP64; reductions use fixed
 // trees, so results do not depend on scheduling.
 
 #include <hip/hip_runtime.h>
@@ -25,11 +28,81 @@
 namespace bse {
 
 // ------------------------------------------------------------------------------------
-// collapse: qbar[(k~ NP + p) n_rhs + r] = sum_z qpart[cell_of_corner(k~, z)][z][r][p]
+// collapse: qbar[(k~ NP + p) n_rhs + r] = s_r sum_z qpart[cell_of_corner(k~, z)][z][r][p]
+//
+// In a chain the collapse closes the step: every block adds the restrict's per-cell
+// ||u||^2 partials (same fixed order in every block), so all blocks agree on
+// b_{i+1} = ||u_{i+1}|| (Eq. bi), the breakdown test and s_{i+1} = 1 / b_{i+1};
+// block 0 writes b_{i+1} and the next copy of the chain state.
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_collapse(const double2* __restrict__ qpart,
-                                                  double2* __restrict__ qbar, const ChainState* __restrict__ chain,
+template <int MODE>
+__global__ __launch_bounds__(256) void k_collapse(const double2* __restrict__ qpart, double2* __restrict__ qbar,
+                                                  const ChainState* __restrict__ cs_in,
+                                                  const StepScalars* __restrict__ pend,
+                                                  const double* __restrict__ rpart, ChainState* __restrict__ cs_out,
+                                                  double* __restrict__ beta, int ldb, int step, double tol2,
                                                   int n_c, int np, int n_rhs, int64_t total) {
+    __shared__ double sred[kBlock / kWave];
+    __shared__ double sscale[kMaxRhs];
+    const int ncells = n_c * n_c * n_c;
+    if (MODE != COLLAPSE_PLAIN) {
+        for (int r = 0; r < n_rhs; ++r) {
+            const double uu = block_sum_strided(rpart + r * 2, ncells, n_rhs * 2, sred);
+            const double pp = (MODE == COLLAPSE_INIT) ? block_sum_strided(rpart + r * 2 + 1, ncells, n_rhs * 2, sred)
+                                                      : 0.0;
+            if (threadIdx.x != 0) continue;
+            ChainState nx;
+            double b = 0.0;
+            if (MODE == COLLAPSE_INIT) {
+                nx.pnorm2 = pp;
+                nx.s_prev = 0.0;
+                nx.b_cur = 0.0;
+                nx.steps = 0;
+                nx.pad = 0;
+                if (uu > 0.0 && isfinite(uu)) {
+                    nx.active = 1;
+                    nx.s_cur = 1.0 / sqrt(uu);
+                    nx.status = BSE_OK;
+                } else {
+                    nx.active = 0;
+                    nx.s_cur = 0.0;
+                    nx.status = (uu == 0.0) ? BSE_INFO_ZERO_START : BSE_ERR_NONFINITE;
+                }
+            } else {
+                const ChainState st = cs_in[r];
+                nx = st;
+                nx.s_prev = st.s_cur;
+                nx.s_cur = 0.0;
+                nx.b_cur = 0.0;
+                if (st.active) {
+                    const StepScalars sc = pend[r];
+                    if (!sc.ok) {
+                        nx.status = BSE_ERR_NONFINITE;
+                        nx.active = 0;
+                    } else {
+                        nx.steps = step + 1;   // a_{step+1} is valid
+                        if (!isfinite(uu)) {
+                            nx.status = BSE_ERR_NONFINITE;
+                            nx.active = 0;
+                        } else if (uu <= tol2 * sc.ww) {
+                            nx.status = BSE_INFO_INVARIANT_SUBSPACE;  // b_{i+1} = 0: exact chain end
+                            nx.active = 0;
+                        } else {
+                            b = sqrt(uu);
+                            nx.b_cur = b;
+                            nx.s_cur = 1.0 / b;
+                        }
+                    }
+                }
+            }
+            sscale[r] = nx.s_cur;
+            if (blockIdx.x == 0) {
+                cs_out[r] = nx;
+                if (MODE == COLLAPSE_STEP && b > 0.0) beta[(int64_t)r * ldb + step + 1] = b;
+            }
+        }
+        __syncthreads();
+    }
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
     const int r = (int)(i % n_rhs);
@@ -43,13 +116,10 @@ __global__ __launch_bounds__(256) void k_collapse(const double2* __restrict__ qp
         re += v.x;
         im += v.y;
     }
-    const double s = chain ? chain[r].s_cur : 1.0;   // psi = s u in a chain
-    qbar[i] = make_double2(s * re, s * im);
+    const double sc = (MODE == COLLAPSE_PLAIN) ? 1.0 : sscale[r];   // psi = s u in a chain
+    qbar[i] = make_double2(sc * re, sc * im);
 }
 
-// ------------------------------------------------------------------------------------
-// chain outputs and counters
-// ------------------------------------------------------------------------------------
 __global__ void k_chain_report(const ChainState* __restrict__ chain, double* pnorm2, int32_t* steps,
                                int32_t* status, int n_rhs) {
     const int r = threadIdx.x;
@@ -58,11 +128,6 @@ __global__ void k_chain_report(const ChainState* __restrict__ chain, double* pno
         steps[r] = chain[r].steps;
         status[r] = chain[r].status;
     }
-}
-
-__global__ void k_zero_u32(unsigned int* p, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0u;
 }
 
 // ------------------------------------------------------------------------------------
@@ -91,12 +156,12 @@ static hipError_t restrict_dt(const Plan& p, int mode, const void* x, const void
 }
 
 template <int NV, int NC>
-static hipError_t prolong_dt(const Plan& p, int mode, const void* x, void* out, int step, double* a, int lda,
-                             int n_rhs, hipStream_t s) {
+static hipError_t prolong_dt(const Plan& p, int mode, const void* x, void* out, int step, int n_rhs,
+                             hipStream_t s) {
     switch (p.g.dtype) {
-        case BSE_F64: return prolong_launch<double2, double2, NV, NC>(p, mode, x, out, step, a, lda, n_rhs, s);
-        case BSE_F32: return prolong_launch<float2, float2, NV, NC>(p, mode, x, out, step, a, lda, n_rhs, s);
-        default: return prolong_launch<float2, double2, NV, NC>(p, mode, x, out, step, a, lda, n_rhs, s);
+        case BSE_F64: return prolong_launch<double2, double2, NV, NC>(p, mode, x, out, step, n_rhs, s);
+        case BSE_F32: return prolong_launch<float2, float2, NV, NC>(p, mode, x, out, step, n_rhs, s);
+        default: return prolong_launch<float2, double2, NV, NC>(p, mode, x, out, step, n_rhs, s);
     }
 }
 
@@ -111,42 +176,44 @@ hipError_t launch_restrict(const Plan& p, int mode, const void* x, const void* w
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_prolong(const Plan& p, int mode, const void* x, void* out, int step, double* a,
-                          double* b, int lda, int ldb, int n_rhs, hipStream_t s) {
-    (void)b;
-    (void)ldb;
+hipError_t launch_prolong(const Plan& p, int mode, const void* x, void* out, int step, int n_rhs, hipStream_t s) {
     const int nv = p.g.nv, nc = p.g.nc;
 #define BSE_CASE(a_, b_) \
-    if (nv == a_ && nc == b_) return prolong_dt<a_, b_>(p, mode, x, out, step, a, lda, n_rhs, s);
+    if (nv == a_ && nc == b_) return prolong_dt<a_, b_>(p, mode, x, out, step, n_rhs, s);
     BSE_BANDS(BSE_CASE)
 #undef BSE_CASE
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_collapse(const Plan& p, int n_rhs, bool scaled, hipStream_t s) {
+hipError_t launch_collapse(const Plan& p, int mode, int step, double* b, int ldb, int n_rhs, hipStream_t s) {
     const Geometry& g = p.g;
     const int64_t total = g.Nc * n_rhs;
     const int nb = (int)((total + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_collapse, dim3(nb), dim3(kBlock), 0, s,
-                       reinterpret_cast<const double2*>(p.ws + p.L.qpart),
-                       reinterpret_cast<double2*>(p.ws + p.L.qbar),
-                       scaled ? reinterpret_cast<const ChainState*>(p.ws + p.L.chain) : nullptr, g.n_c, g.np, n_rhs,
-                       total);
+    const double2* qpart = reinterpret_cast<const double2*>(p.ws + p.L.qpart);
+    double2* qbar = reinterpret_cast<double2*>(p.ws + p.L.qbar);
+    ChainState* cs = reinterpret_cast<ChainState*>(p.ws + p.L.chain);
+    const StepScalars* pend = reinterpret_cast<const StepScalars*>(p.ws + p.L.pend);
+    const double* rpart = reinterpret_cast<const double*>(p.ws + p.L.rpart);
+    const double tol = breakdown_tol(g.dtype);
+    // the chain start writes copy 0, step i reads copy i % 2 and writes copy (i + 1) % 2
+    const ChainState* cin = cs + state_in(step) * kMaxRhs;
+    ChainState* cout = (mode == COLLAPSE_INIT) ? cs : cs + state_out(step) * kMaxRhs;
+    if (mode == COLLAPSE_PLAIN)
+        hipLaunchKernelGGL(k_collapse<COLLAPSE_PLAIN>, dim3(nb), dim3(kBlock), 0, s, qpart, qbar, cin, pend, rpart,
+                           cout, b, ldb, step, tol * tol, g.n_c, g.np, n_rhs, total);
+    else if (mode == COLLAPSE_INIT)
+        hipLaunchKernelGGL(k_collapse<COLLAPSE_INIT>, dim3(nb), dim3(kBlock), 0, s, qpart, qbar, cin, pend, rpart,
+                           cout, b, ldb, step, tol * tol, g.n_c, g.np, n_rhs, total);
+    else
+        hipLaunchKernelGGL(k_collapse<COLLAPSE_STEP>, dim3(nb), dim3(kBlock), 0, s, qpart, qbar, cin, pend, rpart,
+                           cout, b, ldb, step, tol * tol, g.n_c, g.np, n_rhs, total);
     return hipGetLastError();
 }
 
-hipError_t launch_chain_report(const Plan& p, double* pnorm2, int32_t* steps, int32_t* status, int n_rhs,
-                               hipStream_t s) {
-    hipLaunchKernelGGL(k_chain_report, dim3(1), dim3(kWave), 0, s,
-                       reinterpret_cast<const ChainState*>(p.ws + p.L.chain), pnorm2, steps, status, n_rhs);
-    return hipGetLastError();
-}
-
-hipError_t launch_zero_counters(const Plan& p, hipStream_t s) {
-    // counters are contiguous: gcount, pcount, rcount (256-byte regions)
-    const int64_t n = (int64_t)((p.L.rcount + 256 - p.L.gcount) / sizeof(unsigned int));
-    hipLaunchKernelGGL(k_zero_u32, dim3(8), dim3(kBlock), 0, s,
-                       reinterpret_cast<unsigned int*>(p.ws + p.L.gcount), n);
+hipError_t launch_chain_report(const Plan& p, int n_steps, double* pnorm2, int32_t* steps, int32_t* status,
+                               int n_rhs, hipStream_t s) {
+    const ChainState* cs = reinterpret_cast<const ChainState*>(p.ws + p.L.chain) + state_in(n_steps) * kMaxRhs;
+    hipLaunchKernelGGL(k_chain_report, dim3(1), dim3(kWave), 0, s, cs, pnorm2, steps, status, n_rhs);
     return hipGetLastError();
 }
 

@@ -4,8 +4,8 @@
 //
 // One block per coarse cell; wavefront = right-hand side, lane = subpoint, so each
 // lane owns its output block and nothing is reduced across lanes.  In a chain the
-// block also forms FP64 partials of <u_i|w> and ||w||^2 and the last block turns
-// them into a_i (Eq. ai).
+// block also writes its FP64 partials of <u_i|w> and ||w||^2, from which the next
+// kernel forms a_i (Eq. ai).
 //
 // Main form (n_div^3 <= 64): the block stages the overlaps of one corner at a time
 // in LDS with coalesced loads, double-buffered (the loads for corner z+1 are in
@@ -26,13 +26,10 @@ template <class M2, class V2, int NV, int NC, int MODE>
 __global__ __launch_bounds__(256) void k_prolong1(const M2* __restrict__ d, const double* __restrict__ delta,
                                                  const double2* __restrict__ rvec, const V2* __restrict__ x,
                                                  V2* __restrict__ out, double* __restrict__ ppart,
-                                                 unsigned int* __restrict__ pcount, ChainState* __restrict__ chain,
-                                                 double* __restrict__ alpha, int lda, int step, int n_c, int n_div,
+                                                 const ChainState* __restrict__ chain, int n_c, int n_div,
                                                  int neighbours, int64_t N, int n_rhs) {
     constexpr int NP = NV * NC;
     constexpr int NE = NV * NV + NC * NC;
-    __shared__ double red[kBlock / kWave];
-    __shared__ int flag;
     const int ndiv3 = n_div * n_div * n_div;
     const int rhs = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     const int lane = threadIdx.x % kWave;
@@ -110,54 +107,23 @@ __global__ __launch_bounds__(256) void k_prolong1(const M2* __restrict__ d, cons
         ppart[((int64_t)cell * n_rhs + rhs) * 2] = pw;
         ppart[((int64_t)cell * n_rhs + rhs) * 2 + 1] = ww;
     }
-    const int ncells = gridDim.x;
-    if (!last_block_arrival(pcount, (unsigned)ncells, &flag)) return;
-    for (int r = 0; r < n_rhs; ++r) {
-        double s2[2];
-        for (int comp = 0; comp < 2; ++comp) {
-            double v = 0.0;
-            for (int c = threadIdx.x; c < ncells; c += blockDim.x) v += ppart[((int64_t)c * n_rhs + r) * 2 + comp];
-            s2[comp] = block_sum(v, red);
-        }
-        if (threadIdx.x != 0) continue;
-        ChainState st = chain[r];
-        st.a = 0.0;
-        st.ww = 0.0;
-        if (st.active) {
-            const double a = st.s_cur * s2[0];   // a_i = Re <psi_i | w>  (Eq. ai)
-            if (!isfinite(a) || !isfinite(s2[1])) {
-                st.status = BSE_ERR_NONFINITE;
-                st.active = 0;
-                st.s_cur = 0.0;
-            } else {
-                alpha[(int64_t)r * lda + step] = a;
-                st.a = a;
-                st.ww = s2[1];
-                st.steps = step + 1;
-            }
-        }
-        chain[r] = st;
-    }
 }
-
 
 // ---- main form: overlaps staged per corner in LDS ------------------------------------
 constexpr int kProlongBlock = 512;   // 4 right-hand sides x 2 halves
 
 template <class M2, class V2, int NV, int NC, int MODE>
 __global__ __launch_bounds__(512, 2) void k_prolong2(const M2* __restrict__ d, const double* __restrict__ delta,
-                                                  const double2* __restrict__ rvec, const V2* __restrict__ x,
-                                                  V2* __restrict__ out, double* __restrict__ ppart,
-                                                  unsigned int* __restrict__ pcount, ChainState* __restrict__ chain,
-                                                  double* __restrict__ alpha, int lda, int step, int n_c, int n_div,
-                                                  int neighbours, int64_t N, int n_rhs) {
+                                                     const double2* __restrict__ rvec, const V2* __restrict__ x,
+                                                     V2* __restrict__ out, double* __restrict__ ppart,
+                                                     const ChainState* __restrict__ chain, int n_c, int n_div,
+                                                     int neighbours, int64_t N, int n_rhs) {
     constexpr int NP = NV * NC;
     constexpr int NE = NV * NV + NC * NC;
     constexpr int NCH = (NC + 1) / 2;
     constexpr int PF = (NE * kWave + kProlongBlock - 1) / kProlongBlock;  // staged elements per thread
     extern __shared__ double2 lds2[];
-    __shared__ double red[kProlongBlock / kWave];
-    __shared__ int flag;
+    __shared__ double red[kMaxRhs][2][2];
     const int ndiv3 = n_div * n_div * n_div;
     const int blk = NE * ndiv3;
     M2* dbuf0 = reinterpret_cast<M2*>(lds2);
@@ -298,40 +264,13 @@ __global__ __launch_bounds__(512, 2) void k_prolong2(const M2* __restrict__ d, c
     pw = wave_sum(pw);
     ww = wave_sum(ww);
     if (wave_on && lane == 0) {
-        double* q = ppart + (((int64_t)cell * n_rhs + rhs) * 2 + h) * 2;
-        q[0] = pw;
-        q[1] = ww;
+        red[rhs][h][0] = pw;
+        red[rhs][h][1] = ww;
     }
-    const int ncells = gridDim.x;
-    if (!last_block_arrival(pcount, (unsigned)ncells, &flag)) return;
-    for (int r = 0; r < n_rhs; ++r) {
-        double s2[2];
-        for (int comp = 0; comp < 2; ++comp) {
-            double v = 0.0;
-            for (int c = t; c < ncells; c += blockDim.x) {
-                const double* q = ppart + ((int64_t)c * n_rhs + r) * 4;
-                v += q[comp] + q[2 + comp];
-            }
-            s2[comp] = block_sum(v, red);
-        }
-        if (t != 0) continue;
-        ChainState stt = chain[r];
-        stt.a = 0.0;
-        stt.ww = 0.0;
-        if (stt.active) {
-            const double a = stt.s_cur * s2[0];   // a_i = Re <psi_i | w>  (Eq. ai)
-            if (!isfinite(a) || !isfinite(s2[1])) {
-                stt.status = BSE_ERR_NONFINITE;
-                stt.active = 0;
-                stt.s_cur = 0.0;
-            } else {
-                alpha[(int64_t)r * lda + step] = a;
-                stt.a = a;
-                stt.ww = s2[1];
-                stt.steps = step + 1;
-            }
-        }
-        chain[r] = stt;
+    __syncthreads();
+    if (t < 2 * n_rhs) {   // both halves of a right-hand side, fixed order
+        const int r = t >> 1, comp = t & 1;
+        ppart[((int64_t)cell * n_rhs + r) * 2 + comp] = red[r][0][comp] + red[r][1][comp];
     }
 }
 
@@ -340,13 +279,11 @@ static size_t prolong2_lds(int ne, int ndiv3, int np, int n_rhs, size_t melem) {
 }
 
 template <class M2, class V2, int NV, int NC>
-hipError_t prolong_launch(const Plan& p, int mode, const void* x, void* out, int step, double* a, int lda,
-                          int n_rhs, hipStream_t s) {
+hipError_t prolong_launch(const Plan& p, int mode, const void* x, void* out, int step, int n_rhs, hipStream_t s) {
     const Geometry& g = p.g;
     const double2* rvec = reinterpret_cast<const double2*>(p.ws + p.L.rvec);
     double* ppart = reinterpret_cast<double*>(p.ws + p.L.ppart);
-    unsigned int* pcount = reinterpret_cast<unsigned int*>(p.ws + p.L.pcount);
-    ChainState* chain = reinterpret_cast<ChainState*>(p.ws + p.L.chain);
+    const ChainState* cs = reinterpret_cast<const ChainState*>(p.ws + p.L.chain) + state_in(step) * kMaxRhs;
     const M2* d = reinterpret_cast<const M2*>(p.d);
     const V2* xv = reinterpret_cast<const V2*>(x);
     V2* ov = reinterpret_cast<V2*>(out);
@@ -356,25 +293,24 @@ hipError_t prolong_launch(const Plan& p, int mode, const void* x, void* out, int
         dim3 grid(g.ncells), block(kProlongBlock);
         if (mode == PROLONG_PLAIN)
             hipLaunchKernelGGL((k_prolong2<M2, V2, NV, NC, PROLONG_PLAIN>), grid, block, lds, s, d, p.delta, rvec, xv,
-                               ov, ppart, pcount, chain, nullptr, 0, 0, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
+                               ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
         else
             hipLaunchKernelGGL((k_prolong2<M2, V2, NV, NC, PROLONG_LANCZOS>), grid, block, lds, s, d, p.delta, rvec,
-                               xv, ov, ppart, pcount, chain, a, lda, step, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
+                               xv, ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
     } else {
         dim3 grid(g.ncells), block(kWave * n_rhs);
         if (mode == PROLONG_PLAIN)
             hipLaunchKernelGGL((k_prolong1<M2, V2, NV, NC, PROLONG_PLAIN>), grid, block, 0, s, d, p.delta, rvec, xv,
-                               ov, ppart, pcount, chain, nullptr, 0, 0, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
+                               ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
         else
             hipLaunchKernelGGL((k_prolong1<M2, V2, NV, NC, PROLONG_LANCZOS>), grid, block, 0, s, d, p.delta, rvec,
-                               xv, ov, ppart, pcount, chain, a, lda, step, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
+                               xv, ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
     }
     return hipGetLastError();
 }
 
 #define BSE_PROLONG_INST(M2, V2, A, B)                                                                             \
-    template hipError_t prolong_launch<M2, V2, A, B>(const Plan&, int, const void*, void*, int, double*, int, int, \
-                                                     hipStream_t);
+    template hipError_t prolong_launch<M2, V2, A, B>(const Plan&, int, const void*, void*, int, int, hipStream_t);
 #define BSE_PROLONG_ALL(A, B)                 \
     BSE_PROLONG_INST(double2, double2, A, B)  \
     BSE_PROLONG_INST(float2, float2, A, B)    \

@@ -11,9 +11,11 @@
 // contiguous segments.
 //
 // In chain modes the block first forms its slice of the new vector with coalesced
-// element-wise accesses (u_{i+1} = w - a_i psi_i, or u_1 = P) and its squared norm;
-// the last block to finish adds the per-block norms and closes the step
-// (b_{i+1} = ||u_{i+1}||, breakdown and finiteness checks, scale s_{i+1} = 1 / b_{i+1}).
+// element-wise accesses (u_{i+1} = w - a_i psi_i, or u_1 = P) and writes the slice's
+// squared norm; the collapse that follows adds those into b_{i+1}.  a_i itself is
+// the sum of the prolong's per-cell partials, added by every block in the same
+// fixed order (so every block holds the same bits); the block of cell 0 records it.
+// No block waits on another: kernel boundaries order the steps.
 //
 // Block order is XCD-aware: the n_rhs blocks of one cell carry indices that are equal
 // modulo 8, so they run on the same XCD and share its L2 copy of the cell's overlaps.
@@ -33,19 +35,17 @@ __device__ __forceinline__ double xor_sum_j(double v) {
 }
 
 template <class M2, class V2, int NV, int NC, int MODE>
-__global__ __launch_bounds__(256, (NV * NC > 18) ? 2 : 3) void k_restrict2(const M2* __restrict__ d, const V2* x,
-                                                   const V2* __restrict__ psi, const double2* __restrict__ P,
-                                                   V2* out, double2* __restrict__ qpart, ChainState* __restrict__ chain,
-                                                   double* __restrict__ rpart, unsigned int* __restrict__ rcount,
-                                                   double* __restrict__ alpha, double* __restrict__ beta, int lda,
-                                                   int ldb, int step, double tol2, int n_c, int n_div,
-                                                   int neighbours, int64_t N, int n_rhs) {
+__global__ __launch_bounds__(256, (NV * NC > 18) ? 2 : 3) void k_restrict2(
+    const M2* __restrict__ d, const V2* x, const V2* __restrict__ psi, const double2* __restrict__ P, V2* out,
+    double2* __restrict__ qpart, const ChainState* __restrict__ cs, StepScalars* __restrict__ pend,
+    const double* __restrict__ ppart, double* __restrict__ rpart, double* __restrict__ alpha,
+    double* __restrict__ beta, int lda, int ldb, int step, int n_c, int n_div, int neighbours, int64_t N,
+    int n_rhs) {
     constexpr int NP = NV * NC;
     constexpr int NE = NV * NV + NC * NC;
     constexpr int NW = kBlock / kWave;
     __shared__ double2 red[NW][8][NP];
     __shared__ double sred[NW];
-    __shared__ int flag;
     const int ndiv3 = n_div * n_div * n_div;
     const int ncells = n_c * n_c * n_c;
     // XCD-aware block -> (cell, rhs)
@@ -69,15 +69,34 @@ __global__ __launch_bounds__(256, (NV * NC > 18) ? 2 : 3) void k_restrict2(const
         for (int64_t i = tid; i < (int64_t)n_rhs * ldb; i += nth) beta[i] = 0.0;
     }
     if (MODE != RESTRICT_PLAIN) {
-        // init: u_1 = P.  update: u_{i+1} = w - a_i psi_i = w - a_i s_i u_i  (Eq. bi)
-        const double coef = (MODE == RESTRICT_UPDATE) ? chain[rhs].a * chain[rhs].s_cur : 0.0;
+        // init: u_1 = P.  update: u_{i+1} = w - a_i psi_i = w - a_i s_i u_i  (Eq. bi), with
+        // a_i = s_i sum_cells <u_i|w>_cell  (Eq. ai)
+        double coef = 0.0;
+        bool ok = true;
+        if (MODE == RESTRICT_UPDATE) {
+            const double pw = block_sum_strided(ppart + rhs * 2, ncells, n_rhs * 2, sred);
+            const double ww = block_sum_strided(ppart + rhs * 2 + 1, ncells, n_rhs * 2, sred);
+            const ChainState st = cs[rhs];
+            const double a = st.s_cur * pw;
+            ok = st.active && isfinite(a) && isfinite(ww);
+            coef = ok ? a * st.s_cur : 0.0;
+            if (cell == 0 && t == 0 && st.active) {
+                StepScalars sc;
+                sc.a = a;
+                sc.ww = ww;
+                sc.ok = ok;
+                sc.pad[0] = sc.pad[1] = sc.pad[2] = 0;
+                pend[rhs] = sc;
+                if (ok) alpha[(int64_t)rhs * lda + step] = a;
+            }
+        }
         for (int i = t; i < nelem; i += blockDim.x) {
-            cd u;
+            cd u = cmake(0.0, 0.0);
             if (MODE == RESTRICT_INIT) {
                 u = ld(P + base + i);
                 pp = fma(u.re, u.re, pp);
                 pp = fma(u.im, u.im, pp);
-            } else {
+            } else if (ok) {
                 u = ld(x + base + i);
                 const cd ps = ld(psi + base + i);
                 u.re = fma(-coef, ps.re, u.re);
@@ -182,62 +201,12 @@ __global__ __launch_bounds__(256, (NV * NC > 18) ? 2 : 3) void k_restrict2(const
     }
     if (MODE == RESTRICT_PLAIN) return;
 
-    // ||u||^2 (and ||P||^2 at the start): block partials, last block closes the step
+    // ||u||^2 (and ||P||^2 at the start) of this block's slice, for the collapse
     uu = block_sum(uu, sred);
     pp = block_sum(pp, sred);
     if (t == 0) {
         rpart[((int64_t)cell * n_rhs + rhs) * 2] = uu;
         rpart[((int64_t)cell * n_rhs + rhs) * 2 + 1] = pp;
-    }
-    if (!last_block_arrival(rcount, (unsigned)(ncells * n_rhs), &flag)) return;
-    for (int r = 0; r < n_rhs; ++r) {
-        double s2[2];
-        for (int comp = 0; comp < 2; ++comp) {
-            double v = 0.0;
-            for (int c = t; c < ncells; c += blockDim.x) v += rpart[((int64_t)c * n_rhs + r) * 2 + comp];
-            s2[comp] = block_sum(v, sred);
-        }
-        if (t != 0) continue;
-        ChainState st;
-        if (MODE == RESTRICT_INIT) {
-            st.pnorm2 = s2[1];
-            st.a = 0.0;
-            st.b_cur = 0.0;
-            st.s_prev = 0.0;
-            st.ww = 0.0;
-            st.steps = 0;
-            st.pad = 0;
-            if (s2[0] > 0.0 && isfinite(s2[0])) {
-                st.active = 1;
-                st.s_cur = 1.0 / sqrt(s2[0]);
-                st.status = BSE_OK;
-            } else {
-                st.active = 0;
-                st.s_cur = 0.0;
-                st.status = (s2[0] == 0.0) ? BSE_INFO_ZERO_START : BSE_ERR_NONFINITE;
-            }
-        } else {
-            st = chain[r];
-            st.s_prev = st.s_cur;
-            st.s_cur = 0.0;
-            st.b_cur = 0.0;
-            if (st.active) {
-                const double b2 = s2[0];
-                if (!isfinite(b2)) {
-                    st.status = BSE_ERR_NONFINITE;
-                    st.active = 0;
-                } else if (b2 <= tol2 * st.ww) {
-                    st.status = BSE_INFO_INVARIANT_SUBSPACE;  // b_{i+1} = 0: exact chain end
-                    st.active = 0;
-                } else {
-                    const double bb = sqrt(b2);
-                    beta[(int64_t)r * ldb + step + 1] = bb;
-                    st.b_cur = bb;
-                    st.s_cur = 1.0 / bb;
-                }
-            }
-        }
-        chain[r] = st;
     }
 }
 
@@ -246,27 +215,26 @@ hipError_t restrict_launch(const Plan& p, int mode, const void* x, const void* w
                            void* out, int step, double* a, double* b, int lda, int ldb, int n_rhs, hipStream_t s) {
     const Geometry& g = p.g;
     double2* qpart = reinterpret_cast<double2*>(p.ws + p.L.qpart);
-    ChainState* chain = reinterpret_cast<ChainState*>(p.ws + p.L.chain);
+    const ChainState* cs = reinterpret_cast<const ChainState*>(p.ws + p.L.chain) + state_in(step) * kMaxRhs;
+    StepScalars* pend = reinterpret_cast<StepScalars*>(p.ws + p.L.pend);
+    const double* ppart = reinterpret_cast<const double*>(p.ws + p.L.ppart);
     double* rpart = reinterpret_cast<double*>(p.ws + p.L.rpart);
-    unsigned int* rcount = reinterpret_cast<unsigned int*>(p.ws + p.L.rcount);
     const M2* d = reinterpret_cast<const M2*>(p.d);
-    // breakdown: b_{i+1} <= tol ||w||
-    const double tol = (sizeof(V2) == sizeof(float2)) ? 1e-6 : 1e-12;
     const int groups = (g.ncells + 7) / 8;
     dim3 grid(groups * 8 * n_rhs), block(kBlock);
     if (mode == RESTRICT_PLAIN)
         hipLaunchKernelGGL((k_restrict2<M2, V2, NV, NC, RESTRICT_PLAIN>), grid, block, 0, s, d,
-                           reinterpret_cast<const V2*>(x), nullptr, nullptr, nullptr, qpart, chain, rpart, rcount,
-                           nullptr, nullptr, 0, 0, 0, 0.0, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
+                           reinterpret_cast<const V2*>(x), nullptr, nullptr, nullptr, qpart, cs, pend, ppart, rpart,
+                           nullptr, nullptr, 0, 0, 0, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
     else if (mode == RESTRICT_UPDATE)
         hipLaunchKernelGGL((k_restrict2<M2, V2, NV, NC, RESTRICT_UPDATE>), grid, block, 0, s, d,
                            reinterpret_cast<const V2*>(w), reinterpret_cast<const V2*>(psi), nullptr,
-                           reinterpret_cast<V2*>(out), qpart, chain, rpart, rcount, a, b, lda, ldb, step, tol * tol,
-                           g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
+                           reinterpret_cast<V2*>(out), qpart, cs, pend, ppart, rpart, a, b, lda, ldb, step, g.n_c,
+                           g.n_div, g.neighbours, g.N, n_rhs);
     else
         hipLaunchKernelGGL((k_restrict2<M2, V2, NV, NC, RESTRICT_INIT>), grid, block, 0, s, d, nullptr, nullptr,
-                           reinterpret_cast<const double2*>(P), reinterpret_cast<V2*>(out), qpart, chain, rpart,
-                           rcount, a, b, lda, ldb, 0, tol * tol, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
+                           reinterpret_cast<const double2*>(P), reinterpret_cast<V2*>(out), qpart, cs, pend, ppart,
+                           rpart, a, b, lda, ldb, 0, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
     return hipGetLastError();
 }
 
