@@ -23,7 +23,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-FP32_VALU_TFLOPS = 157.3       # published vector FP32 peak
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_gemv2_restrict2_prolong2_c1_f32_hbm_counters.md")
+GEMV_SOURCE = os.path.join(ROOT, "paper_1602_01863_amd", "csrc", "gemv.hip")
+
+
+def measured_traffic(workload: str, dtype: str):
+    """HBM bytes per coarse-product launch from the committed rocprofv3 counter
+    summary, or None if it does not cover this workload or the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    import re
+
+    if workload != "c1" or dtype != "f32" or not os.path.exists(COUNTER_SUMMARY):
+        return None
+    text = open(COUNTER_SUMMARY).read()
+    m_t = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    m_h = re.search(r"gemv_source_sha256_16:\s*([0-9a-f]+)", text)
+    if not (m_t and m_h):
+        return None
+    digest = hashlib.sha256(open(GEMV_SOURCE, "rb").read()).hexdigest()[:16]
+    return int(m_t.group(1)) if digest == m_h.group(1) else None
 
 
 def _args():
@@ -150,13 +169,14 @@ def main():
             "engine": "VALU FP64 FMA on FP32 storage (HBM-bound; no MFMA)",
         },
         "roofline": {
-            "kernel": "k_gemv (coarse product r = K_c qbar)",
+            "kernel": "coarse product r = K_c qbar (k_gemv2 + k_gemv_reduce)",
             "bound": "hbm",
             "achieved": round(achieved_gbs, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(args.config, dtype),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },
         "time_to_eps2_s": round(t_eps, 4),
         "setup_s": round(t_setup, 3),

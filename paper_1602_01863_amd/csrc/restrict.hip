@@ -123,8 +123,9 @@ __global__ __launch_bounds__(256, (NV * NC > 18) ? 2 : 3) void k_restrict2(
         for (int q = 0; q < NCH; ++q) acc[v][q] = cmake(0.0, 0.0);
     // overlaps of (cell, z) and the block's vector slice through buffer resources:
     // one per-lane offset, element strides in scalar offsets
+    // (the resource must be wavefront-uniform: the cell's 8 corner blocks, corner in the lane offset)
     const __amdgpu_buffer_rsrc_t rd =
-        make_rsrc(d + ((int64_t)(cell * 8 + z) * NE) * ndiv3, (uint32_t)(NE * ndiv3 * sizeof(M2)));
+        make_rsrc(d + (int64_t)cell * 8 * NE * ndiv3, (uint32_t)(8 * NE * ndiv3 * sizeof(M2)));
     const __amdgpu_buffer_rsrc_t rx = make_rsrc(src + base, (uint32_t)(nelem * sizeof(V2)));
     const int es = ndiv3 * (int)sizeof(M2);
 #pragma unroll 1
@@ -132,7 +133,7 @@ __global__ __launch_bounds__(256, (NV * NC > 18) ? 2 : 3) void k_restrict2(
         const int sub = 4 * s + j;
         if (sub >= ndiv3) continue;
         const double f = prefactor(sub, z, n_div, neighbours);
-        const int vd = sub * (int)sizeof(M2);
+        const int vd = (z * NE * ndiv3 + sub) * (int)sizeof(M2);
         const int vx = sub * NP * (int)sizeof(V2);
         M2 dv[NV * NV];
 #pragma unroll
