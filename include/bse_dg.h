@@ -153,7 +153,11 @@ bse_status bse_build_coarse_kernel(const bse_dims* dims, const double* vecs_coar
  *   workspace  device, >= bse_workspace_bytes(dims) bytes, 256-byte aligned; owned
  *              by the plan until bse_plan_destroy; its contents need no
  *              initialisation; one plan must not run on two streams at once.
- *   stream     reserved (nothing is enqueued).
+ *              Besides scratch space it holds the restrict tiles: a copy of d
+ *              re-ordered for the restrict kernel, with the valence blocks already
+ *              multiplied by the prefactors f (Sec. 3).
+ *   stream     the copy is written by a kernel enqueued on this stream; later calls
+ *              on the plan must be ordered after it (same stream, or synchronised).
  */
 bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d,
                            const double* delta, void* workspace, size_t workspace_bytes,

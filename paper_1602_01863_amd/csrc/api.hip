@@ -78,6 +78,7 @@ bool make_geometry(const bse_dims* d, Geometry* g) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+static constexpr int kWaveHost = 64;  // lanes of a wavefront (restrict tile width)
 static size_t vec_elem_bytes(int dtype) { return dtype == BSE_F32 ? sizeof(float2) : sizeof(double2); }
 static size_t mat_elem_bytes(int dtype) { return dtype == BSE_F64 ? sizeof(double2) : sizeof(float2); }
 
@@ -100,6 +101,14 @@ Layout make_layout(const Geometry& g) {
     L.pend = take((size_t)kMaxRhs * sizeof(StepScalars));
     L.vec_a = take((size_t)g.N * R * vec_elem_bytes(g.dtype));
     L.vec_b = take((size_t)g.N * R * vec_elem_bytes(g.dtype));
+    L.dsw_bytes = 0;
+    L.dsw = off;
+    if (supported_bands(g.nv, g.nc) && restrict_tile_lds(g) > 0) {
+        const int eb = (int)mat_elem_bytes(g.dtype);
+        const SwzShape z = swz_shape(g.nv, g.nc, g.ndiv3, eb);
+        L.dsw_bytes = (size_t)g.ncells * z.S * kWaveHost * z.kp * eb;
+        L.dsw = take(L.dsw_bytes);
+    }
     L.total = off;
     return L;
 }
@@ -268,7 +277,12 @@ bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d, 
     p->ev_used = 0;
     p->timed_ms = 0.0;
     p->timed_launches = 0;
-    (void)stream;
+    // restrict tiles: a re-ordered copy of the overlaps in the workspace
+    hipError_t e = launch_swizzle(*p, stream);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "bse_plan_create");
+    }
     *plan_out = reinterpret_cast<bse_plan*>(p);
     return BSE_OK;
 }

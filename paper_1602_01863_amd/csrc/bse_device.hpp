@@ -86,13 +86,46 @@ __device__ __forceinline__ double2 bload<double2>(__amdgpu_buffer_rsrc_t r, int 
     return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
-// ---- interpolation prefactors (Sec. 3) ----------------------------------------------
-// f^l_j = 1 - j/n for l = 0 and j/n for l = 1.
-__device__ __forceinline__ double axis_weight(int j, int n, int l) {
-    double t = (double)j / (double)n;
-    return l ? t : 1.0 - t;
+// ---- 16-byte load units ---------------------------------------------------------------
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+// complex entries per 16-byte unit and the unit's type, by storage precision
+template <class M2>
+struct Unit16;
+template <>
+struct Unit16<float2> {
+    static constexpr int P = 2;
+    using t = f4v;
+    __device__ static inline float2 get(const f4v& v, int i) {
+        return i == 0 ? make_float2(v.x, v.y) : make_float2(v.z, v.w);
+    }
+};
+template <>
+struct Unit16<double2> {
+    static constexpr int P = 1;
+    using t = d2v;
+    __device__ static inline double2 get(const d2v& v, int) { return make_double2(v.x, v.y); }
+};
+
+// ---- lane-pair exchange (lanes 2i <-> 2i+1) through DPP quad permutation [1,0,3,2] ------
+__device__ __forceinline__ int swap_pair_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ float2 swap_pair(float2 v) {
+    return make_float2(__builtin_bit_cast(float, swap_pair_i(__builtin_bit_cast(int, v.x))),
+                       __builtin_bit_cast(float, swap_pair_i(__builtin_bit_cast(int, v.y))));
 }
-// trilinear f^{lmn}(sub) = f^l_{j1} f^m_{j2} f^n_{j3}, corner z = 4l + 2m + n;
+__device__ __forceinline__ double swap_pair_d(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = swap_pair_i((int)(b & 0xffffffffll));
+    const int hi = swap_pair_i((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double2 swap_pair(double2 v) { return make_double2(swap_pair_d(v.x), swap_pair_d(v.y)); }
+
+// ---- interpolation prefactors (Sec. 3) ----------------------------------------------
+// f^l_j = 1 - j/n for l = 0 and j/n for l = 1, so the trilinear
+// f^{lmn}(sub) = f^l_{j1} f^m_{j2} f^n_{j3} (corner z = 4l + 2m + n) is an integer
+// product over n^3: one correctly rounded division.
 // neighbours == 1: one-hot on the nearest corner (j/n <= 1/2 picks l = 0 per axis).
 __device__ __forceinline__ double prefactor(int sub, int z, int n_div, int neighbours) {
     int j3 = sub % n_div;
@@ -103,7 +136,8 @@ __device__ __forceinline__ double prefactor(int sub, int z, int n_div, int neigh
         int l1 = (2 * j1 > n_div), m1 = (2 * j2 > n_div), n1 = (2 * j3 > n_div);
         return (l == l1 && m == m1 && n == n1) ? 1.0 : 0.0;
     }
-    return axis_weight(j1, n_div, l) * axis_weight(j2, n_div, m) * axis_weight(j3, n_div, n);
+    const int num = (l ? j1 : n_div - j1) * (m ? j2 : n_div - j2) * (n ? j3 : n_div - j3);
+    return (double)num / (double)(n_div * n_div * n_div);
 }
 
 // coarse index of corner z of a cell (periodic wrap), Eq. (neighborhood)
@@ -151,10 +185,18 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 
 // Sum of n doubles at p[i * stride] (i < n) by the whole block, in an order that
 // depends only on n and blockDim: every block that calls it on the same data gets
-// the same bits.  `lds` holds blockDim.x / 64 doubles.
+// the same bits.  `lds` holds blockDim.x / 64 doubles.  Loads go in batches of 4
+// per thread with clamped indices, so a batch is in flight at once.
 __device__ __forceinline__ double block_sum_strided(const double* p, int n, int stride, double* lds) {
     double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[(int64_t)i * stride];
+    for (int i0 = 0; i0 < n; i0 += 4 * (int)blockDim.x) {
+        double x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] = p[(int64_t)min(i0 + (int)threadIdx.x + q * (int)blockDim.x, n - 1) * stride];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (i0 + (int)threadIdx.x + q * (int)blockDim.x < n) v += x[q];
+    }
     return block_sum(v, lds);
 }
 

@@ -45,9 +45,33 @@ struct Geometry {
 
 bool make_geometry(const bse_dims* d, Geometry* g);
 
-// workspace regions (byte offsets from the workspace base)
+// Restrict tiles: the overlaps re-ordered for the restrict's lanes (see restrict.hip).
+// Tile (cell, s) covers subpoints 4 s .. 4 s + 3 of the cell; every lane of the
+// wavefront owns kp entries, stored as 16-byte units.
+struct SwzShape {
+    int ndv;   // valence-block entries per lane (half of nv^2, rounded up)
+    int nch;   // conduction columns n2 per lane (half of nc, rounded up)
+    int kl;    // entries per lane: ndv + nc * nch
+    int unit;  // complex entries per 16-byte unit (2 for FP32, 1 for FP64 storage)
+    int kp;    // kl rounded up to a multiple of unit
+    int S;     // tiles per cell: ceil(n_div^3 / 4)
+};
+__host__ __device__ inline SwzShape swz_shape(int nv, int nc, int ndiv3, int elem_bytes) {
+    SwzShape z;
+    z.ndv = (nv * nv + 1) / 2;
+    z.nch = (nc + 1) / 2;
+    z.kl = z.ndv + nc * z.nch;
+    z.unit = 16 / elem_bytes;
+    z.kp = (z.kl + z.unit - 1) / z.unit * z.unit;
+    z.S = (ndiv3 + 3) / 4;
+    return z;
+}
+
+// workspace regions (byte offsets from the workspace base); dsw_bytes == 0 when the
+// restrict reads the overlaps in their input layout
 struct Layout {
-    size_t qpart, qbar, rvec, gpart, ppart, rpart, chain, pend, vec_a, vec_b;
+    size_t qpart, qbar, rvec, gpart, ppart, rpart, chain, pend, vec_a, vec_b, dsw;
+    size_t dsw_bytes;
     size_t total;
 };
 Layout make_layout(const Geometry& g);
@@ -80,6 +104,11 @@ hipError_t launch_prolong(const Plan& p, int mode, const void* x, void* out_prev
 hipError_t launch_chain_report(const Plan& p, int n_steps, double* pnorm2, int32_t* steps, int32_t* status,
                                int n_rhs, hipStream_t s);
 bool supported_bands(int nv, int nc);
+
+// restrict tiles from the overlaps (restrict.hip), enqueued at plan creation
+hipError_t launch_swizzle(const Plan& p, hipStream_t s);
+// vector slice of a cell held in LDS by the tiled restrict: bytes, or 0 if it does not fit
+size_t restrict_tile_lds(const Geometry& g);
 
 // setup launches implemented in setup.hip
 hipError_t launch_overlaps(const Geometry& g, const double* vc, const double* vd, void* dout, hipStream_t s);

@@ -22,9 +22,6 @@
 
 namespace bse {
 
-typedef float f4v __attribute__((ext_vector_type(4)));
-typedef double d2v __attribute__((ext_vector_type(2)));
-
 template <class M2>
 struct Gv;
 template <>

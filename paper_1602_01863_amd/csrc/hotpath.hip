@@ -6,9 +6,9 @@
 // formed without an extra pass over memory:
 //   k_gemv2     r = K_c qbar by column splits, k_gemv_reduce adds the splits
 //               (gemv.hip; Eq. matmul2, corner sum collapsed)
-//   k_prolong2  w = delta psi_i + C^H r - b_i psi_{i-1} and a_i   (prolong.hip;
+//   k_prolong3  w = delta psi_i + C^H r - b_i psi_{i-1} and a_i   (prolong.hip;
 //               Eq. matmul3, Eq. bse1 diagonal, Eq. ai)
-//   k_restrict2 u_{i+1} = w - a_i psi_i, b_{i+1} = ||u_{i+1}||, then the
+//   k_restrict3 u_{i+1} = w - a_i psi_i, b_{i+1} = ||u_{i+1}||, then the
 //               per-(cell, corner) coarse vectors of u_{i+1}  (restrict.hip;
 //               Eqs. bi, ci, matmul1)
 //   k_collapse  qbar(k~) = s_{i+1} x sum of the 8 (cell, corner) vectors on k~

@@ -8,9 +8,9 @@
 // kernel forms a_i (Eq. ai).
 //
 // Main form (n_div^3 <= 64): the block stages the overlaps of one corner at a time
-// in LDS with coalesced loads, double-buffered (the loads for corner z+1 are in
-// flight while corner z is computed), so every wavefront of the cell reads them from
-// LDS; the 8 coarse blocks r_{k~z} sit in LDS as well.  Two wavefronts per
+// in LDS with coalesced 16-byte loads, double-buffered (the loads for corner z+1 are
+// in flight while corner z is computed), so every wavefront of the cell reads them
+// from LDS; the 8 coarse blocks r_{k~z} sit in LDS as well.  Two wavefronts per
 // right-hand side split the conduction index c in halves, which halves the FP64
 // accumulators each lane holds.
 
@@ -110,83 +110,100 @@ __global__ __launch_bounds__(256) void k_prolong1(const M2* __restrict__ d, cons
 }
 
 // ---- main form: overlaps staged per corner in LDS ------------------------------------
-constexpr int kProlongBlock = 512;   // 4 right-hand sides x 2 halves
+//
+// Block = 2 NR wavefronts (NR right-hand sides x 2 halves of c), so that two blocks
+// share a compute unit and no wavefront idles.  The prefactors f(sub, z) of the cell
+// sit in an LDS table; the diagonal, the -b_i psi_{i-1} term and the chain partials
+// are applied after the corner loop, so psi_i is read once.
+// wavefronts per SIMD the register budget allows: 3 (<= 168 VGPRs) where the
+// FP32-storage variant fits without spills, else 2
+template <class M2, int NV, int NC>
+constexpr int prolong3_waves() {
+    return (sizeof(M2) == 8 && NV * NC <= 18 && !(NV == 3 && NC == 4)) ? 3 : 2;
+}
 
-template <class M2, class V2, int NV, int NC, int MODE>
-__global__ __launch_bounds__(512, 2) void k_prolong2(const M2* __restrict__ d, const double* __restrict__ delta,
-                                                     const double2* __restrict__ rvec, const V2* __restrict__ x,
-                                                     V2* __restrict__ out, double* __restrict__ ppart,
-                                                     const ChainState* __restrict__ chain, int n_c, int n_div,
-                                                     int neighbours, int64_t N, int n_rhs) {
+// threads of a block: 2 wavefronts per right-hand side, at least 4 wavefronts (the
+// extra ones only help staging)
+template <int NR>
+constexpr int prolong3_threads() {
+    return 128 * (NR < 2 ? 2 : NR);
+}
+
+template <class M2, class V2, int NV, int NC, int MODE, int NR>
+__global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, NV, NC>())) void k_prolong3(const M2* __restrict__ d, const double* __restrict__ delta,
+                                                         const double2* __restrict__ rvec, const V2* __restrict__ x,
+                                                         V2* __restrict__ out, double* __restrict__ ppart,
+                                                         const ChainState* __restrict__ chain, int n_c, int n_div,
+                                                         int neighbours, int64_t N) {
     constexpr int NP = NV * NC;
     constexpr int NE = NV * NV + NC * NC;
     constexpr int NCH = (NC + 1) / 2;
-    constexpr int PF = (NE * kWave + kProlongBlock - 1) / kProlongBlock;  // staged elements per thread
+    constexpr int NT = prolong3_threads<NR>();
+    using U = Unit16<M2>;
+    using Rw = typename U::t;
+    constexpr int PFU = (NE * kWave / U::P + NT - 1) / NT;  // staged 16-byte units per thread (n_div^3 <= 64)
     extern __shared__ double2 lds2[];
-    __shared__ double red[kMaxRhs][2][2];
+    __shared__ double red[NR][2][2];
+    __shared__ double ftab[8 * kWave];
     const int ndiv3 = n_div * n_div * n_div;
-    const int blk = NE * ndiv3;
-    M2* dbuf0 = reinterpret_cast<M2*>(lds2);
-    M2* dbuf1 = dbuf0 + blk;
-    double2* rs = lds2 + (2 * blk * (int)sizeof(M2) + 15) / 16;
+    const int blk = NE * ndiv3;                // entries of one (cell, corner) block
+    const int blku = (blk + U::P - 1) / U::P;  // its 16-byte units (blocks start 16-byte aligned)
+    Rw* dbuf0 = reinterpret_cast<Rw*>(lds2);
+    Rw* dbuf1 = dbuf0 + blku;
+    double2* rs = lds2 + 2 * blku;
     const int cell = blockIdx.x;
     const int t = threadIdx.x;
     const int wave = t / kWave;
     const int lane = t % kWave;
     const int rhs = wave >> 1;
     const int h = wave & 1;
-    const bool wave_on = rhs < n_rhs;
-    const bool active = wave_on && lane < ndiv3;
+    const bool active = lane < ndiv3 && rhs < NR;
 
-    // coarse blocks r_{k~z} of the 8 corners: rs[z][p][r]
-    const int per = NP * n_rhs;
-    for (int i = t; i < 8 * per; i += blockDim.x) {
-        const int zz = i / per;
-        rs[i] = rvec[(int64_t)corner_index(cell, zz, n_c) * per + (i - zz * per)];
+    // coarse blocks r_{k~z} of the 8 corners: rs[z][p][r]; prefactor table; corner 0
+    constexpr int per = NP * NR;
+    static_assert(8 * per <= 2 * NT, "coarse blocks: two entries per thread");
+    {
+        double2 rv[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int i = min(t + q * NT, 8 * per - 1);
+            const int zz = i / per;
+            rv[q] = rvec[(int64_t)corner_index(cell, zz, n_c) * per + (i - zz * per)];
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (t + q * NT < 8 * per) rs[t + q * NT] = rv[q];
     }
-    const M2* dcell = d + (int64_t)cell * 8 * blk;
-    for (int i = t; i < blk; i += blockDim.x) dbuf0[i] = dcell[i];
+    for (int i = t; i < 8 * ndiv3; i += NT) ftab[(i / ndiv3) * kWave + i % ndiv3] = prefactor(i % ndiv3, i / ndiv3, n_div, neighbours);
+    // staging loads are unconditional (indices clamped into the block) so that they
+    // are all in flight together; only the LDS writes are guarded
+    const Rw* dcell = reinterpret_cast<const Rw*>(d + (int64_t)cell * 8 * blk);
+    {
+        Rw pf[PFU];
+#pragma unroll
+        for (int q = 0; q < PFU; ++q) pf[q] = dcell[min(t + q * NT, blku - 1)];
+#pragma unroll
+        for (int q = 0; q < PFU; ++q)
+            if (t + q * NT < blku) dbuf0[t + q * NT] = pf[q];
+    }
 
-    double s_cur = 1.0, c_prev = 0.0;
-    if (MODE == PROLONG_LANCZOS && wave_on) {
-        s_cur = chain[rhs].s_cur;                         // psi_i = s_i u_i
-        c_prev = chain[rhs].b_cur * chain[rhs].s_prev;    // b_i psi_{i-1} = b_i s_{i-1} u_{i-1}
-    }
-    const int64_t kd = (int64_t)cell * ndiv3 + lane;
-    const int64_t t0 = (int64_t)rhs * N + kd * NP;
     cd acc[NV][NCH];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int q = 0; q < NCH; ++q) {
-            acc[v][q] = cmake(0.0, 0.0);
-            const int c = h * NCH + q;
-            if (active && c < NC) {
-                const int p = v * NC + c;
-                const cd xv = ld(x + t0 + p);
-                acc[v][q] = cscale(xv, delta[kd * NP + p] * s_cur);
-                if (MODE == PROLONG_LANCZOS && c_prev != 0.0) {
-                    const cd pv = ld(out + t0 + p);
-                    acc[v][q].re = fma(-c_prev, pv.re, acc[v][q].re);
-                    acc[v][q].im = fma(-c_prev, pv.im, acc[v][q].im);
-                }
-            }
-        }
+        for (int q = 0; q < NCH; ++q) acc[v][q] = cmake(0.0, 0.0);
 
     for (int z = 0; z < 8; ++z) {
-        M2 pf[PF];
+        Rw pf[PFU];
         if (z < 7) {
-            const M2* dn = dcell + (int64_t)(z + 1) * blk;
+            const Rw* dn = dcell + (int64_t)(z + 1) * blku;
 #pragma unroll
-            for (int q = 0; q < PF; ++q) {
-                const int i = t + q * kProlongBlock;
-                if (i < blk) pf[q] = dn[i];
-            }
+            for (int q = 0; q < PFU; ++q) pf[q] = dn[min(t + q * NT, blku - 1)];
         }
         __syncthreads();
-        const M2* cur = (z & 1) ? dbuf1 : dbuf0;
+        const M2* cur = reinterpret_cast<const M2*>((z & 1) ? dbuf1 : dbuf0);
         if (active) {
-            const double f = prefactor(lane, z, n_div, neighbours);
+            const double f = ftab[z * kWave + lane];
             const double2* rz = rs + z * per + rhs;
             M2 dv[NV * NV];   // storage precision, widened at use
 #pragma unroll
@@ -203,7 +220,7 @@ __global__ __launch_bounds__(512, 2) void k_prolong2(const M2* __restrict__ d, c
                 cd rc[NV];
 #pragma unroll
                 for (int n1 = 0; n1 < NV; ++n1) {
-                    const double2 r = rz[(n1 * NC + n2) * n_rhs];
+                    const double2 r = rz[(n1 * NC + n2) * NR];
                     rc[n1] = cmake(r.x, r.y);
                 }
 #pragma unroll
@@ -230,17 +247,25 @@ __global__ __launch_bounds__(512, 2) void k_prolong2(const M2* __restrict__ d, c
                 }
         }
         if (z < 7) {
-            M2* nxt = (z & 1) ? dbuf0 : dbuf1;
+            Rw* nxt = (z & 1) ? dbuf0 : dbuf1;
 #pragma unroll
-            for (int q = 0; q < PF; ++q) {
-                const int i = t + q * kProlongBlock;
-                if (i < blk) nxt[i] = pf[q];
+            for (int q = 0; q < PFU; ++q) {
+                const int i = t + q * NT;
+                if (i < blku) nxt[i] = pf[q];
             }
         }
     }
 
+    // w = delta psi_i + C^H r [- b_i psi_{i-1}], with psi_i = s_i u_i in a chain
+    double s_cur = 1.0, c_prev = 0.0;
+    if (MODE == PROLONG_LANCZOS && rhs < NR) {
+        s_cur = chain[rhs].s_cur;                         // psi_i = s_i u_i
+        c_prev = chain[rhs].b_cur * chain[rhs].s_prev;    // b_i psi_{i-1} = b_i s_{i-1} u_{i-1}
+    }
     double pw = 0.0, ww = 0.0;
     if (active) {
+        const int64_t kd = (int64_t)cell * ndiv3 + lane;
+        const int64_t t0 = (int64_t)rhs * N + kd * NP;
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -248,14 +273,23 @@ __global__ __launch_bounds__(512, 2) void k_prolong2(const M2* __restrict__ d, c
                 const int c = h * NCH + q;
                 if (c >= NC) continue;
                 const int p = v * NC + c;
-                st(out + t0 + p, acc[v][q]);
+                const cd xv = ld(x + t0 + p);
+                const double dl = delta[kd * NP + p] * s_cur;
+                cd w = acc[v][q];
+                w.re = fma(dl, xv.re, w.re);
+                w.im = fma(dl, xv.im, w.im);
+                if (MODE == PROLONG_LANCZOS && c_prev != 0.0) {
+                    const cd pv = ld(out + t0 + p);
+                    w.re = fma(-c_prev, pv.re, w.re);
+                    w.im = fma(-c_prev, pv.im, w.im);
+                }
+                st(out + t0 + p, w);
                 if (MODE == PROLONG_LANCZOS) {
-                    const cd w = rounded(acc[v][q], out);
-                    const cd xv = ld(x + t0 + p);
-                    pw = fma(xv.re, w.re, pw);
-                    pw = fma(xv.im, w.im, pw);
-                    ww = fma(w.re, w.re, ww);
-                    ww = fma(w.im, w.im, ww);
+                    const cd wr = rounded(w, out);
+                    pw = fma(xv.re, wr.re, pw);
+                    pw = fma(xv.im, wr.im, pw);
+                    ww = fma(wr.re, wr.re, ww);
+                    ww = fma(wr.im, wr.im, ww);
                 }
             }
     }
@@ -263,19 +297,36 @@ __global__ __launch_bounds__(512, 2) void k_prolong2(const M2* __restrict__ d, c
 
     pw = wave_sum(pw);
     ww = wave_sum(ww);
-    if (wave_on && lane == 0) {
+    if (lane == 0 && rhs < NR) {
         red[rhs][h][0] = pw;
         red[rhs][h][1] = ww;
     }
     __syncthreads();
-    if (t < 2 * n_rhs) {   // both halves of a right-hand side, fixed order
+    if (t < 2 * NR) {   // both halves of a right-hand side, fixed order
         const int r = t >> 1, comp = t & 1;
-        ppart[((int64_t)cell * n_rhs + r) * 2 + comp] = red[r][0][comp] + red[r][1][comp];
+        ppart[((int64_t)cell * NR + r) * 2 + comp] = red[r][0][comp] + red[r][1][comp];
     }
 }
 
-static size_t prolong2_lds(int ne, int ndiv3, int np, int n_rhs, size_t melem) {
-    return (2 * (size_t)ne * ndiv3 * melem + 15) / 16 * 16 + (size_t)8 * np * n_rhs * sizeof(double2);
+static size_t prolong3_lds(int ne, int ndiv3, int np, int n_rhs, size_t melem) {
+    const size_t blku = ((size_t)ne * ndiv3 * melem + 15) / 16;
+    return 2 * blku * 16 + (size_t)8 * np * n_rhs * sizeof(double2);
+}
+
+template <class M2, class V2, int NV, int NC, int NR>
+static void prolong3_go(const Plan& p, int mode, const V2* xv, V2* ov, const ChainState* cs, size_t lds,
+                        hipStream_t s) {
+    const Geometry& g = p.g;
+    const double2* rvec = reinterpret_cast<const double2*>(p.ws + p.L.rvec);
+    double* ppart = reinterpret_cast<double*>(p.ws + p.L.ppart);
+    const M2* d = reinterpret_cast<const M2*>(p.d);
+    dim3 grid(g.ncells), block(prolong3_threads<NR>());
+    if (mode == PROLONG_PLAIN)
+        hipLaunchKernelGGL((k_prolong3<M2, V2, NV, NC, PROLONG_PLAIN, NR>), grid, block, lds, s, d, p.delta, rvec, xv,
+                           ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N);
+    else
+        hipLaunchKernelGGL((k_prolong3<M2, V2, NV, NC, PROLONG_LANCZOS, NR>), grid, block, lds, s, d, p.delta, rvec,
+                           xv, ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N);
 }
 
 template <class M2, class V2, int NV, int NC>
@@ -288,15 +339,16 @@ hipError_t prolong_launch(const Plan& p, int mode, const void* x, void* out, int
     const V2* xv = reinterpret_cast<const V2*>(x);
     V2* ov = reinterpret_cast<V2*>(out);
     constexpr int NP = NV * NC, NE = NV * NV + NC * NC;
-    const size_t lds = prolong2_lds(NE, g.ndiv3, NP, n_rhs, sizeof(M2));
-    if (g.ndiv3 <= kWave && lds <= 64 * 1024) {
-        dim3 grid(g.ncells), block(kProlongBlock);
-        if (mode == PROLONG_PLAIN)
-            hipLaunchKernelGGL((k_prolong2<M2, V2, NV, NC, PROLONG_PLAIN>), grid, block, lds, s, d, p.delta, rvec, xv,
-                               ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
-        else
-            hipLaunchKernelGGL((k_prolong2<M2, V2, NV, NC, PROLONG_LANCZOS>), grid, block, lds, s, d, p.delta, rvec,
-                               xv, ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
+    const size_t lds = prolong3_lds(NE, g.ndiv3, NP, n_rhs, sizeof(M2));
+    // staged form: whole 16-byte units per (cell, corner) block and an aligned base
+    const bool units = ((size_t)NE * g.ndiv3 * sizeof(M2)) % 16 == 0 && ((uintptr_t)p.d & 15) == 0;
+    if (g.ndiv3 <= kWave && lds <= 64 * 1024 && units) {
+        switch (n_rhs) {
+            case 1: prolong3_go<M2, V2, NV, NC, 1>(p, mode, xv, ov, cs, lds, s); break;
+            case 2: prolong3_go<M2, V2, NV, NC, 2>(p, mode, xv, ov, cs, lds, s); break;
+            case 3: prolong3_go<M2, V2, NV, NC, 3>(p, mode, xv, ov, cs, lds, s); break;
+            default: prolong3_go<M2, V2, NV, NC, 4>(p, mode, xv, ov, cs, lds, s); break;
+        }
     } else {
         dim3 grid(g.ncells), block(kWave * n_rhs);
         if (mode == PROLONG_PLAIN)

@@ -211,6 +211,274 @@ __global__ __launch_bounds__(256, (NV * NC > 18) ? 2 : 3) void k_restrict2(
     }
 }
 
+// ---- tiled form: overlaps from restrict tiles, the vector slice from LDS ------------------
+//
+// Same lane roles as k_restrict2 (lane = 8 z + 2 j + h, subpoint 4 s + j), but every
+// value a lane needs comes from a restrict tile (one contiguous 1 KiB run per 16-byte
+// load of the wavefront) or from the block's vector slice in LDS.  The tile carries
+// f(sub, z) Dv already (f is real, so conj(f Dv) = f conj(Dv)) and each lane of a pair
+// h = 0, 1 holds half of the valence block; the halves are exchanged with a DPP
+// permutation.  The slice in LDS is padded with zeros to 4 S subpoints.
+
+// tile entry k of lane l in (cell, s): see swz_shape()
+template <class M2>
+__global__ __launch_bounds__(256) void k_swizzle(const M2* __restrict__ d, M2* __restrict__ dsw, int ndiv3, int n_div,
+                                                 int nv, int nc, int neighbours, int64_t total) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const SwzShape z = swz_shape(nv, nc, ndiv3, (int)sizeof(M2));
+    const int ne = nv * nv + nc * nc;
+    const int nunit = z.kp / z.unit;
+    const int kin = (int)(idx % z.unit);
+    int64_t rest = idx / z.unit;
+    const int lane = (int)(rest % kWave);
+    rest /= kWave;
+    const int q = (int)(rest % nunit);
+    rest /= nunit;
+    const int s = (int)(rest % z.S);
+    const int64_t cell = rest / z.S;
+    const int k = q * z.unit + kin;
+    const int corner = lane >> 3, j = (lane >> 1) & 3, h = lane & 1;
+    const int sub = 4 * s + j;
+    cd v = cmake(0.0, 0.0);
+    if (sub < ndiv3 && k < z.kl) {
+        const M2* blk = d + (cell * 8 + corner) * ne * ndiv3 + sub;
+        if (k < z.ndv) {
+            const int e = h * z.ndv + k;
+            if (e < nv * nv) v = cscale(ld(blk + (int64_t)e * ndiv3), prefactor(sub, corner, n_div, neighbours));
+        } else {
+            const int kk = k - z.ndv;
+            const int c = kk / z.nch, n2 = h * z.nch + kk % z.nch;
+            if (n2 < nc) v = ld(blk + (int64_t)(nv * nv + c * nc + n2) * ndiv3);
+        }
+    }
+    st(dsw + idx, v);
+}
+
+template <class M2, class V2, int NV, int NC, int MODE>
+__global__ __launch_bounds__(256, (NV * NC > 18) ? 2 : 3) void k_restrict3(
+    const M2* __restrict__ dsw, const V2* x, const V2* __restrict__ psi, const double2* __restrict__ P, V2* out,
+    double2* __restrict__ qpart, const ChainState* __restrict__ cs, StepScalars* __restrict__ pend,
+    const double* __restrict__ ppart, double* __restrict__ rpart, double* __restrict__ alpha,
+    double* __restrict__ beta, int lda, int ldb, int step, int n_c, int n_div, int64_t N, int n_rhs) {
+    constexpr int NP = NV * NC;
+    constexpr int NW = kBlock / kWave;
+    constexpr int NDV = (NV * NV + 1) / 2;
+    constexpr int NCH = (NC + 1) / 2;
+    constexpr int KL = NDV + NC * NCH;
+    using U = Unit16<M2>;
+    using R = typename U::t;
+    constexpr int NU = (KL + U::P - 1) / U::P;  // 16-byte loads per lane and tile
+    extern __shared__ double2 xs_raw[];
+    V2* xs = reinterpret_cast<V2*>(xs_raw);
+    __shared__ double2 red[NW][8][NP];
+    __shared__ double sred[NW];
+    const int ndiv3 = n_div * n_div * n_div;
+    const int ncells = n_c * n_c * n_c;
+    const int S = (ndiv3 + 3) / 4;
+    // XCD-aware block -> (cell, rhs), as in k_restrict2
+    const int bid = blockIdx.x;
+    const int rest = bid / 8;
+    const int rhs = rest % n_rhs;
+    const int cell = (rest / n_rhs) * 8 + bid % 8;
+    if (cell >= ncells) return;
+    const int t = threadIdx.x;
+    const int wave = t / kWave;
+    const int lane = t % kWave;
+    const int64_t base = (int64_t)rhs * N + (int64_t)cell * ndiv3 * NP;
+    const int nelem = ndiv3 * NP;
+    double uu = 0.0, pp = 0.0;
+
+    if (MODE == RESTRICT_INIT) {
+        const int64_t tid = (int64_t)(cell * n_rhs + rhs) * blockDim.x + t;
+        const int64_t nth = (int64_t)ncells * n_rhs * blockDim.x;
+        for (int64_t i = tid; i < (int64_t)n_rhs * lda; i += nth) alpha[i] = 0.0;
+        for (int64_t i = tid; i < (int64_t)n_rhs * ldb; i += nth) beta[i] = 0.0;
+    }
+    // element-wise passes run in batches of EPT elements per thread whose loads are
+    // unconditional (clamped indices), so each batch is in flight at once
+    constexpr int EPT = 8;
+    if (MODE == RESTRICT_PLAIN) {
+        for (int i0 = 0; i0 < nelem; i0 += EPT * kBlock) {
+            V2 xv[EPT];
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) xv[e] = x[base + min(i0 + t + e * kBlock, nelem - 1)];
+#pragma unroll
+            for (int e = 0; e < EPT; ++e)
+                if (i0 + t + e * kBlock < nelem) xs[i0 + t + e * kBlock] = xv[e];
+        }
+    } else {
+        // init: u_1 = P.  update: u_{i+1} = w - a_i psi_i = w - a_i s_i u_i  (Eq. bi),
+        // a_i = s_i sum_cells <u_i|w>_cell  (Eq. ai)
+        double coef = 0.0;
+        bool ok = true;
+        if (MODE == RESTRICT_UPDATE) {
+            const double pw = block_sum_strided(ppart + rhs * 2, ncells, n_rhs * 2, sred);
+            const double ww = block_sum_strided(ppart + rhs * 2 + 1, ncells, n_rhs * 2, sred);
+            const ChainState st0 = cs[rhs];
+            const double a = st0.s_cur * pw;
+            ok = st0.active && isfinite(a) && isfinite(ww);
+            coef = ok ? a * st0.s_cur : 0.0;
+            if (cell == 0 && t == 0 && st0.active) {
+                StepScalars sc;
+                sc.a = a;
+                sc.ww = ww;
+                sc.ok = ok;
+                sc.pad[0] = sc.pad[1] = sc.pad[2] = 0;
+                pend[rhs] = sc;
+                if (ok) alpha[(int64_t)rhs * lda + step] = a;
+            }
+        }
+        for (int i0 = 0; i0 < nelem; i0 += EPT * kBlock) {
+            cd ua[EPT], pb[EPT];
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int64_t ic = base + min(i0 + t + e * kBlock, nelem - 1);
+                if (MODE == RESTRICT_INIT) {
+                    ua[e] = ld(P + ic);
+                } else {
+                    ua[e] = ld(x + ic);
+                    pb[e] = ld(psi + ic);
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int i = i0 + t + e * kBlock;
+                if (i >= nelem) continue;
+                cd u = cmake(0.0, 0.0);
+                if (MODE == RESTRICT_INIT) {
+                    u = ua[e];
+                    pp = fma(u.re, u.re, pp);
+                    pp = fma(u.im, u.im, pp);
+                } else if (ok) {
+                    u = ua[e];
+                    u.re = fma(-coef, pb[e].re, u.re);
+                    u.im = fma(-coef, pb[e].im, u.im);
+                }
+                st(out + base + i, u);
+                st(xs + i, u);
+                const cd ur = rounded(u, out);
+                uu = fma(ur.re, ur.re, uu);
+                uu = fma(ur.im, ur.im, uu);
+            }
+        }
+    }
+    for (int i = nelem + t; i < 4 * S * NP; i += blockDim.x) st(xs + i, cmake(0.0, 0.0));
+    __syncthreads();
+
+    const int j = (lane >> 1) & 3;
+    const int h = lane & 1;
+    const int z = lane >> 3;
+    cd acc[NV][NCH];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) acc[v][q] = cmake(0.0, 0.0);
+    const R* tile = reinterpret_cast<const R*>(dsw) + (int64_t)cell * S * NU * kWave + lane;
+#pragma unroll 1
+    for (int s = wave; s < S; s += NW) {
+        R raw[NU];
+        const R* tp = tile + (int64_t)s * NU * kWave;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) raw[u] = tp[u * kWave];
+        auto entry = [&](int k) { return U::get(raw[k / U::P], k % U::P); };
+        const V2* xrow = xs + (4 * s + j) * NP;
+        // T[v][q] = sum_c x[v][c] Dc[c][n2(q)] over this lane's half of n2
+        cd T[NV][NCH];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int q = 0; q < NCH; ++q) T[v][q] = cmake(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            cd xc[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) xc[v] = cv(xrow[v * NC + c]);
+#pragma unroll
+            for (int q = 0; q < NCH; ++q) {
+                const cd dc = cv(entry(NDV + c * NCH + q));
+#pragma unroll
+                for (int v = 0; v < NV; ++v) cfma(T[v][q], xc[v], dc);
+            }
+        }
+        // the pair's halves of f Dv, then acc[n3][q] += sum_v conj(f Dv[v][n3]) T[v][q]
+        cd dv[NDV * 2];
+#pragma unroll
+        for (int k = 0; k < NDV; ++k) {
+            const M2 mine = entry(k);
+            const M2 other = swap_pair(mine);
+            dv[k] = cv(h ? other : mine);
+            dv[NDV + k] = cv(h ? mine : other);
+        }
+#pragma unroll
+        for (int n3 = 0; n3 < NV; ++n3)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const cd dvv = dv[v * NV + n3];
+#pragma unroll
+                for (int q = 0; q < NCH; ++q) cfma_cj(acc[n3][q], dvv, T[v][q]);
+            }
+    }
+    // sum the 4 subpoint columns of each (corner, half), then the wavefronts
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) {
+            acc[v][q].re = xor_sum_j(acc[v][q].re);
+            acc[v][q].im = xor_sum_j(acc[v][q].im);
+        }
+    if (j == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int q = 0; q < NCH; ++q) {
+                const int n4 = h * NCH + q;
+                if (n4 < NC) red[wave][z][v * NC + n4] = make_double2(acc[v][q].re, acc[v][q].im);
+            }
+    }
+    __syncthreads();
+    for (int o = t; o < 8 * NP; o += blockDim.x) {
+        const int zz = o / NP, p = o % NP;
+        double re = 0.0, im = 0.0;
+        for (int w = 0; w < NW; ++w) {
+            re += red[w][zz][p].x;
+            im += red[w][zz][p].y;
+        }
+        qpart[((int64_t)(cell * 8 + zz) * n_rhs + rhs) * NP + p] = make_double2(re, im);
+    }
+    if (MODE == RESTRICT_PLAIN) return;
+
+    uu = block_sum(uu, sred);
+    pp = block_sum(pp, sred);
+    if (t == 0) {
+        rpart[((int64_t)cell * n_rhs + rhs) * 2] = uu;
+        rpart[((int64_t)cell * n_rhs + rhs) * 2 + 1] = pp;
+    }
+}
+
+size_t restrict_tile_lds(const Geometry& g) {
+    const size_t vb = g.dtype == BSE_F32 ? sizeof(float2) : sizeof(double2);
+    const size_t bytes = (size_t)4 * ((g.ndiv3 + 3) / 4) * g.np * vb;
+    return bytes <= 48 * 1024 ? bytes : 0;
+}
+
+hipError_t launch_swizzle(const Plan& p, hipStream_t s) {
+    const Geometry& g = p.g;
+    if (p.L.dsw_bytes == 0) return hipSuccess;
+    const int eb = g.dtype == BSE_F64 ? (int)sizeof(double2) : (int)sizeof(float2);
+    const int64_t total = (int64_t)(p.L.dsw_bytes / eb);
+    dim3 grid((unsigned)((total + kBlock - 1) / kBlock)), block(kBlock);
+    if (g.dtype == BSE_F64)
+        hipLaunchKernelGGL(k_swizzle<double2>, grid, block, 0, s, reinterpret_cast<const double2*>(p.d),
+                           reinterpret_cast<double2*>(p.ws + p.L.dsw), g.ndiv3, g.n_div, g.nv, g.nc, g.neighbours,
+                           total);
+    else
+        hipLaunchKernelGGL(k_swizzle<float2>, grid, block, 0, s, reinterpret_cast<const float2*>(p.d),
+                           reinterpret_cast<float2*>(p.ws + p.L.dsw), g.ndiv3, g.n_div, g.nv, g.nc, g.neighbours,
+                           total);
+    return hipGetLastError();
+}
+
 template <class M2, class V2, int NV, int NC>
 hipError_t restrict_launch(const Plan& p, int mode, const void* x, const void* w, const void* psi, const double* P,
                            void* out, int step, double* a, double* b, int lda, int ldb, int n_rhs, hipStream_t s) {
@@ -223,6 +491,24 @@ hipError_t restrict_launch(const Plan& p, int mode, const void* x, const void* w
     const M2* d = reinterpret_cast<const M2*>(p.d);
     const int groups = (g.ncells + 7) / 8;
     dim3 grid(groups * 8 * n_rhs), block(kBlock);
+    if (p.L.dsw_bytes > 0) {
+        const M2* dsw = reinterpret_cast<const M2*>(p.ws + p.L.dsw);
+        const size_t lds = restrict_tile_lds(g);
+        if (mode == RESTRICT_PLAIN)
+            hipLaunchKernelGGL((k_restrict3<M2, V2, NV, NC, RESTRICT_PLAIN>), grid, block, lds, s, dsw,
+                               reinterpret_cast<const V2*>(x), nullptr, nullptr, nullptr, qpart, cs, pend, ppart,
+                               rpart, nullptr, nullptr, 0, 0, 0, g.n_c, g.n_div, g.N, n_rhs);
+        else if (mode == RESTRICT_UPDATE)
+            hipLaunchKernelGGL((k_restrict3<M2, V2, NV, NC, RESTRICT_UPDATE>), grid, block, lds, s, dsw,
+                               reinterpret_cast<const V2*>(w), reinterpret_cast<const V2*>(psi), nullptr,
+                               reinterpret_cast<V2*>(out), qpart, cs, pend, ppart, rpart, a, b, lda, ldb, step,
+                               g.n_c, g.n_div, g.N, n_rhs);
+        else
+            hipLaunchKernelGGL((k_restrict3<M2, V2, NV, NC, RESTRICT_INIT>), grid, block, lds, s, dsw, nullptr,
+                               nullptr, reinterpret_cast<const double2*>(P), reinterpret_cast<V2*>(out), qpart, cs,
+                               pend, ppart, rpart, a, b, lda, ldb, 0, g.n_c, g.n_div, g.N, n_rhs);
+        return hipGetLastError();
+    }
     if (mode == RESTRICT_PLAIN)
         hipLaunchKernelGGL((k_restrict2<M2, V2, NV, NC, RESTRICT_PLAIN>), grid, block, 0, s, d,
                            reinterpret_cast<const V2*>(x), nullptr, nullptr, nullptr, qpart, cs, pend, ppart, rpart,
