@@ -217,6 +217,11 @@ bse_status bse_plan_get_timing(bse_plan* plan, double* total_ms, int64_t* launch
 /* Tunables of the coarse product: column splits (0 = automatic).  For sweeps. */
 bse_status bse_plan_set_gemv_splits(bse_plan* plan, int32_t n_split);
 
+/* Tunable of the restrict (Eq. matmul1): right-hand sides handled by one block, 1
+ * (default) or 3 (used only when a call has exactly three right-hand sides).  Both
+ * give the same results; only the speed differs.  For sweeps. */
+bse_status bse_plan_set_restrict_group(bse_plan* plan, int32_t rhs_per_block);
+
 #ifdef __cplusplus
 }
 #endif

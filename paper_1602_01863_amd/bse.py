@@ -39,7 +39,7 @@ EXPORTED = [
     "bse_overlaps_bytes", "bse_build_overlaps", "bse_build_transition_energies",
     "bse_build_coarse_kernel", "bse_plan_create", "bse_plan_destroy", "bse_interp_matvec",
     "bse_haydock_run", "bse_continued_fraction", "bse_plan_set_timing", "bse_plan_get_timing",
-    "bse_plan_set_gemv_splits",
+    "bse_plan_set_gemv_splits", "bse_plan_set_restrict_group",
 ]
 
 
@@ -82,6 +82,7 @@ def _load():
         "bse_plan_set_timing": (i32, [vp, i32]),
         "bse_plan_get_timing": (i32, [vp, P(dbl), P(i64)]),
         "bse_plan_set_gemv_splits": (i32, [vp, i32]),
+        "bse_plan_set_restrict_group": (i32, [vp, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -193,6 +194,10 @@ def bse_plan_get_timing(plan):
 
 def bse_plan_set_gemv_splits(plan, n_split: int):
     _check(_lib.bse_plan_set_gemv_splits(plan, int(n_split)), "bse_plan_set_gemv_splits")
+
+
+def bse_plan_set_restrict_group(plan, rhs_per_block: int):
+    _check(_lib.bse_plan_set_restrict_group(plan, int(rhs_per_block)), "bse_plan_set_restrict_group")
 
 
 # ---- one Hamiltonian on the device ------------------------------------------------------

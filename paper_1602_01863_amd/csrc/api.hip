@@ -271,6 +271,7 @@ bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d, 
     p->delta = delta;
     p->ws = static_cast<char*>(workspace);
     p->n_split = 0;
+    p->restrict_group = 1;
     p->timing = false;
     p->ev = nullptr;
     p->ev_cap = 0;
@@ -434,6 +435,15 @@ bse_status bse_plan_set_gemv_splits(bse_plan* plan, int32_t n_split) {
         return BSE_ERR_INVALID_ARG;
     }
     reinterpret_cast<Plan*>(plan)->n_split = n_split;
+    return BSE_OK;
+}
+
+bse_status bse_plan_set_restrict_group(bse_plan* plan, int32_t rhs_per_block) {
+    if (!plan || (rhs_per_block != 1 && rhs_per_block != 3)) {
+        set_error("bse_plan_set_restrict_group: rhs_per_block must be 1 or 3");
+        return BSE_ERR_INVALID_ARG;
+    }
+    reinterpret_cast<Plan*>(plan)->restrict_group = rhs_per_block;
     return BSE_OK;
 }
 

@@ -84,6 +84,7 @@ struct Plan {
     const double* delta;
     char* ws;
     int n_split;  // 0 = automatic
+    int restrict_group;  // right-hand sides per restrict block (1, or 3 for three)
     // timing of the coarse product
     bool timing;
     int ev_used;

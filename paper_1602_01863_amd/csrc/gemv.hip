@@ -164,10 +164,17 @@ __global__ __launch_bounds__(256) void k_gemv_reduce(const double2* __restrict__
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= n_out) return;
     double re = 0.0, im = 0.0;
-    for (int t = 0; t < n_split; ++t) {
-        const double2 v = part[(int64_t)t * n_out + o];
-        re += v.x;
-        im += v.y;
+    // batches of 8 splits, loads unconditional (clamped) so a batch is in flight at once
+    for (int t0 = 0; t0 < n_split; t0 += 8) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)min(t0 + u, n_split - 1) * n_out + o];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (t0 + u < n_split) {
+                re += v[u].x;
+                im += v[u].y;
+            }
     }
     rout[o] = make_double2(re, im);
 }

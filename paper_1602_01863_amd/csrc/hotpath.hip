@@ -42,14 +42,56 @@ __global__ __launch_bounds__(256) void k_collapse(const double2* __restrict__ qp
                                                   const double* __restrict__ rpart, ChainState* __restrict__ cs_out,
                                                   double* __restrict__ beta, int ldb, int step, double tol2,
                                                   int n_c, int np, int n_rhs, int64_t total) {
-    __shared__ double sred[kBlock / kWave];
+    __shared__ double sred[2 * kMaxRhs][kBlock / kWave];
     __shared__ double sscale[kMaxRhs];
     const int ncells = n_c * n_c * n_c;
+    // this thread's 8 (cell, corner) vectors: loaded first (indices clamped), so their
+    // latency overlaps the chain reductions below
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ic = i < total ? i : total - 1;
+    const int r0 = (int)(ic % n_rhs);
+    const int64_t T = ic / n_rhs;
+    const int p = (int)(T % np);
+    const int k = (int)(T / np);
+    double2 qv[8];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) qv[z] = qpart[((int64_t)(cell_of_corner(k, z, n_c) * 8 + z) * n_rhs + r0) * np + p];
     if (MODE != COLLAPSE_PLAIN) {
+        // per-thread partial sums of ||u||^2 (and ||P||^2) for every right-hand side,
+        // then one block reduction in a fixed order
+        const int nval = 2 * n_rhs;
+        double acc[2 * kMaxRhs];
+#pragma unroll
+        for (int q = 0; q < 2 * kMaxRhs; ++q) acc[q] = 0.0;
+        for (int c0 = 0; c0 < ncells; c0 += 2 * kBlock) {
+            double v[2][2 * kMaxRhs];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int c = min(c0 + (int)threadIdx.x + u * kBlock, ncells - 1);
+#pragma unroll
+                for (int q = 0; q < 2 * kMaxRhs; ++q) v[u][q] = q < nval ? rpart[(int64_t)c * nval + q] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (c0 + (int)threadIdx.x + u * kBlock < ncells)
+#pragma unroll
+                    for (int q = 0; q < 2 * kMaxRhs; ++q) acc[q] += v[u][q];
+        }
+        const int wave = threadIdx.x / kWave;
+#pragma unroll
+        for (int q = 0; q < 2 * kMaxRhs; ++q) {
+            if (q >= nval) break;
+            const double w = wave_sum(acc[q]);
+            if (threadIdx.x % kWave == 0) sred[q][wave] = w;
+        }
+        __syncthreads();
         for (int r = 0; r < n_rhs; ++r) {
-            const double uu = block_sum_strided(rpart + r * 2, ncells, n_rhs * 2, sred);
-            const double pp = (MODE == COLLAPSE_INIT) ? block_sum_strided(rpart + r * 2 + 1, ncells, n_rhs * 2, sred)
-                                                      : 0.0;
+            double uu = 0.0, pp = 0.0;
+            for (int w = 0; w < kBlock / kWave; ++w) {
+                uu += sred[2 * r][w];
+                pp += sred[2 * r + 1][w];
+            }
+            if (MODE != COLLAPSE_INIT) pp = 0.0;
             if (threadIdx.x != 0) continue;
             ChainState nx;
             double b = 0.0;
@@ -103,20 +145,14 @@ __global__ __launch_bounds__(256) void k_collapse(const double2* __restrict__ qp
         }
         __syncthreads();
     }
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
-    const int r = (int)(i % n_rhs);
-    const int64_t T = i / n_rhs;
-    const int p = (int)(T % np);
-    const int k = (int)(T / np);
     double re = 0.0, im = 0.0;
+#pragma unroll
     for (int z = 0; z < 8; ++z) {
-        const int cell = cell_of_corner(k, z, n_c);
-        const double2 v = qpart[((int64_t)(cell * 8 + z) * n_rhs + r) * np + p];
-        re += v.x;
-        im += v.y;
+        re += qv[z].x;
+        im += qv[z].y;
     }
-    const double sc = (MODE == COLLAPSE_PLAIN) ? 1.0 : sscale[r];   // psi = s u in a chain
+    const double sc = (MODE == COLLAPSE_PLAIN) ? 1.0 : sscale[r0];   // psi = s u in a chain
     qbar[i] = make_double2(sc * re, sc * im);
 }
 

@@ -159,11 +159,15 @@ __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, NV, NC>
     const int h = wave & 1;
     const bool active = lane < ndiv3 && rhs < NR;
 
-    // coarse blocks r_{k~z} of the 8 corners: rs[z][p][r]; prefactor table; corner 0
+    // coarse blocks r_{k~z} of the 8 corners (rs[z][p][r]), the overlaps of corner 0 and
+    // the prefactor table.  The loads are unconditional (indices clamped) and all
+    // issued before the first LDS write, so they are in flight together.
     constexpr int per = NP * NR;
     static_assert(8 * per <= 2 * NT, "coarse blocks: two entries per thread");
+    const Rw* dcell = reinterpret_cast<const Rw*>(d + (int64_t)cell * 8 * blk);
     {
         double2 rv[2];
+        Rw pf[PFU];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int i = min(t + q * NT, 8 * per - 1);
@@ -171,17 +175,13 @@ __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, NV, NC>
             rv[q] = rvec[(int64_t)corner_index(cell, zz, n_c) * per + (i - zz * per)];
         }
 #pragma unroll
+        for (int q = 0; q < PFU; ++q) pf[q] = dcell[min(t + q * NT, blku - 1)];
+        __builtin_amdgcn_sched_barrier(0);
+        for (int i = t; i < 8 * ndiv3; i += NT)
+            ftab[(i / ndiv3) * kWave + i % ndiv3] = prefactor(i % ndiv3, i / ndiv3, n_div, neighbours);
+#pragma unroll
         for (int q = 0; q < 2; ++q)
             if (t + q * NT < 8 * per) rs[t + q * NT] = rv[q];
-    }
-    for (int i = t; i < 8 * ndiv3; i += NT) ftab[(i / ndiv3) * kWave + i % ndiv3] = prefactor(i % ndiv3, i / ndiv3, n_div, neighbours);
-    // staging loads are unconditional (indices clamped into the block) so that they
-    // are all in flight together; only the LDS writes are guarded
-    const Rw* dcell = reinterpret_cast<const Rw*>(d + (int64_t)cell * 8 * blk);
-    {
-        Rw pf[PFU];
-#pragma unroll
-        for (int q = 0; q < PFU; ++q) pf[q] = dcell[min(t + q * NT, blku - 1)];
 #pragma unroll
         for (int q = 0; q < PFU; ++q)
             if (t + q * NT < blku) dbuf0[t + q * NT] = pf[q];
@@ -266,6 +266,20 @@ __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, NV, NC>
     if (active) {
         const int64_t kd = (int64_t)cell * ndiv3 + lane;
         const int64_t t0 = (int64_t)rhs * N + kd * NP;
+        // all loads of the lane first (psi_{i-1} unconditionally: before the second
+        // step its buffer holds no vector, and the select below drops it)
+        V2 xr[NV][NCH], pr[NV][NCH];
+        double dr[NV][NCH];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int q = 0; q < NCH; ++q) {
+                const int p = v * NC + min(h * NCH + q, NC - 1);
+                xr[v][q] = x[t0 + p];
+                dr[v][q] = delta[kd * NP + p];
+                if (MODE == PROLONG_LANCZOS) pr[v][q] = out[t0 + p];
+            }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -273,15 +287,17 @@ __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, NV, NC>
                 const int c = h * NCH + q;
                 if (c >= NC) continue;
                 const int p = v * NC + c;
-                const cd xv = ld(x + t0 + p);
-                const double dl = delta[kd * NP + p] * s_cur;
+                const cd xv = cv(xr[v][q]);
+                const double dl = dr[v][q] * s_cur;
                 cd w = acc[v][q];
                 w.re = fma(dl, xv.re, w.re);
                 w.im = fma(dl, xv.im, w.im);
-                if (MODE == PROLONG_LANCZOS && c_prev != 0.0) {
-                    const cd pv = ld(out + t0 + p);
-                    w.re = fma(-c_prev, pv.re, w.re);
-                    w.im = fma(-c_prev, pv.im, w.im);
+                if (MODE == PROLONG_LANCZOS) {
+                    const cd pv = cv(pr[v][q]);
+                    const double pre = c_prev != 0.0 ? pv.re : 0.0;
+                    const double pim = c_prev != 0.0 ? pv.im : 0.0;
+                    w.re = fma(-c_prev, pre, w.re);
+                    w.im = fma(-c_prev, pim, w.im);
                 }
                 st(out + t0 + p, w);
                 if (MODE == PROLONG_LANCZOS) {

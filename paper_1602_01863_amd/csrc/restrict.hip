@@ -255,8 +255,12 @@ __global__ __launch_bounds__(256) void k_swizzle(const M2* __restrict__ d, M2* _
     st(dsw + idx, v);
 }
 
-template <class M2, class V2, int NV, int NC, int MODE>
-__global__ __launch_bounds__(256, (NV * NC > 18) ? 2 : 3) void k_restrict3(
+// Block = one cell and NR of the n_rhs right-hand sides (rhs0 .. rhs0 + NR - 1), so a
+// tile load feeds NR products.  Blocks of one cell carry indices that are equal modulo
+// 8 (same XCD, shared L2 copy of the tiles).  LDS: the vector slices xs[NR][4 S][NP]
+// (storage precision), then the wavefront partials red[NW][NR][8][NP].
+template <class M2, class V2, int NV, int NC, int MODE, int NR>
+__global__ __launch_bounds__(256, (NR == 1 && sizeof(M2) == 8 && NV * NC <= 18) ? 3 : 2) void k_restrict3(
     const M2* __restrict__ dsw, const V2* x, const V2* __restrict__ psi, const double2* __restrict__ P, V2* out,
     double2* __restrict__ qpart, const ChainState* __restrict__ cs, StepScalars* __restrict__ pend,
     const double* __restrict__ ppart, double* __restrict__ rpart, double* __restrict__ alpha,
@@ -269,197 +273,293 @@ __global__ __launch_bounds__(256, (NV * NC > 18) ? 2 : 3) void k_restrict3(
     using U = Unit16<M2>;
     using R = typename U::t;
     constexpr int NU = (KL + U::P - 1) / U::P;  // 16-byte loads per lane and tile
-    extern __shared__ double2 xs_raw[];
-    V2* xs = reinterpret_cast<V2*>(xs_raw);
-    __shared__ double2 red[NW][8][NP];
-    __shared__ double sred[NW];
+    extern __shared__ double2 lds_raw[];
+    __shared__ double sred[2 * NR][NW];
     const int ndiv3 = n_div * n_div * n_div;
     const int ncells = n_c * n_c * n_c;
     const int S = (ndiv3 + 3) / 4;
-    // XCD-aware block -> (cell, rhs), as in k_restrict2
+    const int xstride = 4 * S * NP;  // entries of one right-hand side's slice in LDS
+    V2* xs = reinterpret_cast<V2*>(lds_raw);
+    double2* red = lds_raw + ((size_t)NR * xstride * sizeof(V2) + 15) / 16;
+    // XCD-aware block -> (cell, group of NR right-hand sides)
+    const int ngrp = n_rhs / NR;
     const int bid = blockIdx.x;
     const int rest = bid / 8;
-    const int rhs = rest % n_rhs;
-    const int cell = (rest / n_rhs) * 8 + bid % 8;
-    if (cell >= ncells) return;
+    const int grp = rest % ngrp;
+    const int cell = (rest / ngrp) * 8 + bid % 8;
+    if (cell >= ncells) return;  // padding blocks
+    const int rhs0 = grp * NR;
     const int t = threadIdx.x;
     const int wave = t / kWave;
     const int lane = t % kWave;
-    const int64_t base = (int64_t)rhs * N + (int64_t)cell * ndiv3 * NP;
-    const int nelem = ndiv3 * NP;
-    double uu = 0.0, pp = 0.0;
+    const int nelem = ndiv3 * NP;  // entries of the cell's slice of one vector
+    const int64_t cbase = (int64_t)cell * nelem;
+    const int ntot = NR * nelem;
 
     if (MODE == RESTRICT_INIT) {
-        const int64_t tid = (int64_t)(cell * n_rhs + rhs) * blockDim.x + t;
-        const int64_t nth = (int64_t)ncells * n_rhs * blockDim.x;
+        const int64_t tid = (int64_t)(cell * ngrp + grp) * blockDim.x + t;
+        const int64_t nth = (int64_t)ncells * ngrp * blockDim.x;
         for (int64_t i = tid; i < (int64_t)n_rhs * lda; i += nth) alpha[i] = 0.0;
         for (int64_t i = tid; i < (int64_t)n_rhs * ldb; i += nth) beta[i] = 0.0;
     }
-    // element-wise passes run in batches of EPT elements per thread whose loads are
-    // unconditional (clamped indices), so each batch is in flight at once
+    const R* tile = reinterpret_cast<const R*>(dsw) + (int64_t)cell * S * NU * kWave + lane;
+    // element-wise passes over (rhs, entry) run in batches of EPT entries per thread
+    // whose loads are unconditional (clamped indices), so a batch is in flight at once;
+    // the first batch is issued before anything waits (the chain scalars below)
     constexpr int EPT = 8;
+    cd ua[EPT], pb[EPT];
+    auto gidx = [&](int f) {
+        const int r = f / nelem;
+        return (int64_t)(rhs0 + r) * N + cbase + (f - r * nelem);
+    };
+    auto load_batch = [&](int f0) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int64_t g = gidx(min(f0 + t + e * kBlock, ntot - 1));
+            if (MODE == RESTRICT_INIT) {
+                ua[e] = ld(P + g);
+            } else {
+                ua[e] = ld(x + g);
+                if (MODE == RESTRICT_UPDATE) pb[e] = ld(psi + g);
+            }
+        }
+    };
+    load_batch(0);
+    __builtin_amdgcn_sched_barrier(0);
+
+    double uu[NR], pp[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) uu[r] = pp[r] = 0.0;
     if (MODE == RESTRICT_PLAIN) {
-        for (int i0 = 0; i0 < nelem; i0 += EPT * kBlock) {
-            V2 xv[EPT];
+        for (int f0 = 0; f0 < ntot; f0 += EPT * kBlock) {
+            if (f0 > 0) load_batch(f0);
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) xv[e] = x[base + min(i0 + t + e * kBlock, nelem - 1)];
-#pragma unroll
-            for (int e = 0; e < EPT; ++e)
-                if (i0 + t + e * kBlock < nelem) xs[i0 + t + e * kBlock] = xv[e];
+            for (int e = 0; e < EPT; ++e) {
+                const int f = f0 + t + e * kBlock;
+                if (f >= ntot) continue;
+                const int r = f / nelem;
+                st(xs + r * xstride + (f - r * nelem), ua[e]);
+            }
         }
     } else {
         // init: u_1 = P.  update: u_{i+1} = w - a_i psi_i = w - a_i s_i u_i  (Eq. bi),
-        // a_i = s_i sum_cells <u_i|w>_cell  (Eq. ai)
-        double coef = 0.0;
-        bool ok = true;
-        if (MODE == RESTRICT_UPDATE) {
-            const double pw = block_sum_strided(ppart + rhs * 2, ncells, n_rhs * 2, sred);
-            const double ww = block_sum_strided(ppart + rhs * 2 + 1, ncells, n_rhs * 2, sred);
-            const ChainState st0 = cs[rhs];
-            const double a = st0.s_cur * pw;
-            ok = st0.active && isfinite(a) && isfinite(ww);
-            coef = ok ? a * st0.s_cur : 0.0;
-            if (cell == 0 && t == 0 && st0.active) {
-                StepScalars sc;
-                sc.a = a;
-                sc.ww = ww;
-                sc.ok = ok;
-                sc.pad[0] = sc.pad[1] = sc.pad[2] = 0;
-                pend[rhs] = sc;
-                if (ok) alpha[(int64_t)rhs * lda + step] = a;
-            }
-        }
-        for (int i0 = 0; i0 < nelem; i0 += EPT * kBlock) {
-            cd ua[EPT], pb[EPT];
+        // a_i = s_i sum_cells <u_i|w>_cell  (Eq. ai), from the prolong's per-cell partials
+        double coef[NR];
+        bool ok[NR];
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                const int64_t ic = base + min(i0 + t + e * kBlock, nelem - 1);
-                if (MODE == RESTRICT_INIT) {
-                    ua[e] = ld(P + ic);
-                } else {
-                    ua[e] = ld(x + ic);
-                    pb[e] = ld(psi + ic);
+        for (int r = 0; r < NR; ++r) {
+            coef[r] = 0.0;
+            ok[r] = true;
+        }
+        if (MODE == RESTRICT_UPDATE) {
+            double acc2[2 * NR];
+#pragma unroll
+            for (int q = 0; q < 2 * NR; ++q) acc2[q] = 0.0;
+            for (int c0 = 0; c0 < ncells; c0 += 2 * kBlock) {
+                double v[2][2 * NR];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int c = min(c0 + t + u * kBlock, ncells - 1);
+#pragma unroll
+                    for (int q = 0; q < 2 * NR; ++q) v[u][q] = ppart[((int64_t)c * n_rhs + rhs0) * 2 + q];
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    if (c0 + t + u * kBlock < ncells)
+#pragma unroll
+                        for (int q = 0; q < 2 * NR; ++q) acc2[q] += v[u][q];
+            }
+#pragma unroll
+            for (int q = 0; q < 2 * NR; ++q) {
+                const double w = wave_sum(acc2[q]);
+                if (lane == 0) sred[q][wave] = w;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                double pw = 0.0, ww = 0.0;
+                for (int w = 0; w < NW; ++w) {
+                    pw += sred[2 * r][w];
+                    ww += sred[2 * r + 1][w];
+                }
+                const ChainState st0 = cs[rhs0 + r];
+                const double a = st0.s_cur * pw;
+                ok[r] = st0.active && isfinite(a) && isfinite(ww);
+                coef[r] = ok[r] ? a * st0.s_cur : 0.0;
+                if (cell == 0 && t == 0 && st0.active) {
+                    StepScalars sc;
+                    sc.a = a;
+                    sc.ww = ww;
+                    sc.ok = ok[r];
+                    sc.pad[0] = sc.pad[1] = sc.pad[2] = 0;
+                    pend[rhs0 + r] = sc;
+                    if (ok[r]) alpha[(int64_t)(rhs0 + r) * lda + step] = a;
                 }
             }
+        }
+        for (int f0 = 0; f0 < ntot; f0 += EPT * kBlock) {
+            if (f0 > 0) load_batch(f0);
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
-                const int i = i0 + t + e * kBlock;
-                if (i >= nelem) continue;
+                const int f = f0 + t + e * kBlock;
+                if (f >= ntot) continue;
+                const int r = f / nelem;
+                const int i = f - r * nelem;
+                double cr = 0.0;
+                bool okr = true;
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+                    if (q == r) {
+                        cr = coef[q];
+                        okr = ok[q];
+                    }
                 cd u = cmake(0.0, 0.0);
                 if (MODE == RESTRICT_INIT) {
                     u = ua[e];
-                    pp = fma(u.re, u.re, pp);
-                    pp = fma(u.im, u.im, pp);
-                } else if (ok) {
+                } else if (okr) {
                     u = ua[e];
-                    u.re = fma(-coef, pb[e].re, u.re);
-                    u.im = fma(-coef, pb[e].im, u.im);
+                    u.re = fma(-cr, pb[e].re, u.re);
+                    u.im = fma(-cr, pb[e].im, u.im);
                 }
-                st(out + base + i, u);
-                st(xs + i, u);
+                st(out + (int64_t)(rhs0 + r) * N + cbase + i, u);
+                st(xs + r * xstride + i, u);
                 const cd ur = rounded(u, out);
-                uu = fma(ur.re, ur.re, uu);
-                uu = fma(ur.im, ur.im, uu);
+                const double n2 = fma(ur.re, ur.re, ur.im * ur.im);
+                const double p2 = (MODE == RESTRICT_INIT) ? fma(u.re, u.re, u.im * u.im) : 0.0;
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+                    if (q == r) {
+                        uu[q] += n2;
+                        pp[q] += p2;
+                    }
             }
         }
     }
-    for (int i = nelem + t; i < 4 * S * NP; i += blockDim.x) st(xs + i, cmake(0.0, 0.0));
+    for (int r = 0; r < NR; ++r)
+        for (int i = nelem + t; i < xstride; i += blockDim.x) st(xs + r * xstride + i, cmake(0.0, 0.0));
+    if (MODE != RESTRICT_PLAIN) {
+        // ||u||^2 (and ||P||^2 at the start) of the cell's slices, for the collapse
+        __syncthreads();  // the chain scalars above have been read from sred
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const double a = wave_sum(uu[r]);
+            const double b = wave_sum(pp[r]);
+            if (lane == 0) {
+                sred[2 * r][wave] = a;
+                sred[2 * r + 1][wave] = b;
+            }
+        }
+    }
     __syncthreads();
+    if (MODE != RESTRICT_PLAIN && t < 2 * NR) {
+        double v = 0.0;
+        for (int w = 0; w < NW; ++w) v += sred[t][w];
+        rpart[((int64_t)cell * n_rhs + rhs0) * 2 + t] = v;
+    }
 
     const int j = (lane >> 1) & 3;
     const int h = lane & 1;
     const int z = lane >> 3;
-    cd acc[NV][NCH];
+    cd acc[NR][NV][NCH];
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
+    for (int rr = 0; rr < NR; ++rr)
 #pragma unroll
-        for (int q = 0; q < NCH; ++q) acc[v][q] = cmake(0.0, 0.0);
-    const R* tile = reinterpret_cast<const R*>(dsw) + (int64_t)cell * S * NU * kWave + lane;
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int q = 0; q < NCH; ++q) acc[rr][v][q] = cmake(0.0, 0.0);
 #pragma unroll 1
     for (int s = wave; s < S; s += NW) {
         R raw[NU];
         const R* tp = tile + (int64_t)s * NU * kWave;
 #pragma unroll
         for (int u = 0; u < NU; ++u) raw[u] = tp[u * kWave];
+        // keep the tile's loads together in front of the arithmetic (the scheduler
+        // would otherwise issue them one by one, each with its own wait)
+        __builtin_amdgcn_sched_barrier(0);
         auto entry = [&](int k) { return U::get(raw[k / U::P], k % U::P); };
-        const V2* xrow = xs + (4 * s + j) * NP;
-        // T[v][q] = sum_c x[v][c] Dc[c][n2(q)] over this lane's half of n2
-        cd T[NV][NCH];
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int q = 0; q < NCH; ++q) T[v][q] = cmake(0.0, 0.0);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            cd xc[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) xc[v] = cv(xrow[v * NC + c]);
-#pragma unroll
-            for (int q = 0; q < NCH; ++q) {
-                const cd dc = cv(entry(NDV + c * NCH + q));
-#pragma unroll
-                for (int v = 0; v < NV; ++v) cfma(T[v][q], xc[v], dc);
-            }
-        }
-        // the pair's halves of f Dv, then acc[n3][q] += sum_v conj(f Dv[v][n3]) T[v][q]
-        cd dv[NDV * 2];
+        // the pair's halves of f Dv (lanes h = 0, 1 hold one half each), kept in
+        // storage precision and widened at use
+        M2 dv[NDV * 2];
 #pragma unroll
         for (int k = 0; k < NDV; ++k) {
             const M2 mine = entry(k);
             const M2 other = swap_pair(mine);
-            dv[k] = cv(h ? other : mine);
-            dv[NDV + k] = cv(h ? mine : other);
+            dv[k] = h ? other : mine;
+            dv[NDV + k] = h ? mine : other;
         }
 #pragma unroll
-        for (int n3 = 0; n3 < NV; ++n3)
+        for (int rr = 0; rr < NR; ++rr) {
+            const V2* xrow = xs + rr * xstride + (4 * s + j) * NP;
+            // for each v: T[q] = sum_c x[v][c] Dc[c][n2(q)] over this lane's half of n2,
+            // then acc[n3][q] += conj(f Dv[v][n3]) T[q]
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const cd dvv = dv[v * NV + n3];
+                cd T[NCH];
 #pragma unroll
-                for (int q = 0; q < NCH; ++q) cfma_cj(acc[n3][q], dvv, T[v][q]);
+                for (int q = 0; q < NCH; ++q) T[q] = cmake(0.0, 0.0);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const cd xc = cv(xrow[v * NC + c]);
+#pragma unroll
+                    for (int q = 0; q < NCH; ++q) cfma(T[q], xc, cv(entry(NDV + c * NCH + q)));
+                }
+#pragma unroll
+                for (int n3 = 0; n3 < NV; ++n3) {
+                    const cd dvv = cv(dv[v * NV + n3]);
+#pragma unroll
+                    for (int q = 0; q < NCH; ++q) cfma_cj(acc[rr][n3][q], dvv, T[q]);
+                }
             }
+        }
     }
     // sum the 4 subpoint columns of each (corner, half), then the wavefronts
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int q = 0; q < NCH; ++q) {
-            acc[v][q].re = xor_sum_j(acc[v][q].re);
-            acc[v][q].im = xor_sum_j(acc[v][q].im);
-        }
-    if (j == 0) {
+    for (int rr = 0; rr < NR; ++rr) {
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int q = 0; q < NCH; ++q) {
-                const int n4 = h * NCH + q;
-                if (n4 < NC) red[wave][z][v * NC + n4] = make_double2(acc[v][q].re, acc[v][q].im);
+                acc[rr][v][q].re = xor_sum_j(acc[rr][v][q].re);
+                acc[rr][v][q].im = xor_sum_j(acc[rr][v][q].im);
             }
     }
+    if (j == 0) {
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr)
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int q = 0; q < NCH; ++q) {
+                    const int n4 = h * NCH + q;
+                    if (n4 < NC)
+                        red[((wave * NR + rr) * 8 + z) * NP + v * NC + n4] =
+                            make_double2(acc[rr][v][q].re, acc[rr][v][q].im);
+                }
+    }
     __syncthreads();
-    for (int o = t; o < 8 * NP; o += blockDim.x) {
-        const int zz = o / NP, p = o % NP;
+    for (int o = t; o < NR * 8 * NP; o += blockDim.x) {
+        const int rr = o / (8 * NP), zp = o % (8 * NP);
+        const int zz = zp / NP, p = zp % NP;
         double re = 0.0, im = 0.0;
         for (int w = 0; w < NW; ++w) {
-            re += red[w][zz][p].x;
-            im += red[w][zz][p].y;
+            const double2 v = red[((w * NR + rr) * 8 + zz) * NP + p];
+            re += v.x;
+            im += v.y;
         }
-        qpart[((int64_t)(cell * 8 + zz) * n_rhs + rhs) * NP + p] = make_double2(re, im);
-    }
-    if (MODE == RESTRICT_PLAIN) return;
-
-    uu = block_sum(uu, sred);
-    pp = block_sum(pp, sred);
-    if (t == 0) {
-        rpart[((int64_t)cell * n_rhs + rhs) * 2] = uu;
-        rpart[((int64_t)cell * n_rhs + rhs) * 2 + 1] = pp;
+        qpart[((int64_t)(cell * 8 + zz) * n_rhs + rhs0 + rr) * NP + p] = make_double2(re, im);
     }
 }
 
-size_t restrict_tile_lds(const Geometry& g) {
+static size_t restrict3_lds(const Geometry& g, int nr) {
     const size_t vb = g.dtype == BSE_F32 ? sizeof(float2) : sizeof(double2);
-    const size_t bytes = (size_t)4 * ((g.ndiv3 + 3) / 4) * g.np * vb;
-    return bytes <= 48 * 1024 ? bytes : 0;
+    const size_t xs = (size_t)nr * 4 * ((g.ndiv3 + 3) / 4) * g.np * vb;
+    return (xs + 15) / 16 * 16 + (size_t)(kBlock / kWave) * nr * 8 * g.np * sizeof(double2);
+}
+
+size_t restrict_tile_lds(const Geometry& g) {
+    const size_t bytes = restrict3_lds(g, 1);
+    return bytes <= 64 * 1024 ? bytes : 0;
 }
 
 hipError_t launch_swizzle(const Plan& p, hipStream_t s) {
@@ -479,6 +579,36 @@ hipError_t launch_swizzle(const Plan& p, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <class M2, class V2, int NV, int NC, int NR>
+static hipError_t restrict3_go(const Plan& p, int mode, const M2* dsw, const void* x, const void* w, const void* psi,
+                               const double* P, void* out, int step, double* a, double* b, int lda, int ldb,
+                               int n_rhs, hipStream_t s) {
+    const Geometry& g = p.g;
+    double2* qpart = reinterpret_cast<double2*>(p.ws + p.L.qpart);
+    const ChainState* cs = reinterpret_cast<const ChainState*>(p.ws + p.L.chain) + state_in(step) * kMaxRhs;
+    StepScalars* pend = reinterpret_cast<StepScalars*>(p.ws + p.L.pend);
+    const double* ppart = reinterpret_cast<const double*>(p.ws + p.L.ppart);
+    double* rpart = reinterpret_cast<double*>(p.ws + p.L.rpart);
+    const size_t lds = restrict3_lds(g, NR);
+    if (lds > 64 * 1024 || n_rhs % NR != 0) return hipErrorInvalidConfiguration;
+    const int groups = (g.ncells + 7) / 8;
+    dim3 grid(groups * 8 * (n_rhs / NR)), block(kBlock);
+    if (mode == RESTRICT_PLAIN)
+        hipLaunchKernelGGL((k_restrict3<M2, V2, NV, NC, RESTRICT_PLAIN, NR>), grid, block, lds, s, dsw,
+                           reinterpret_cast<const V2*>(x), nullptr, nullptr, nullptr, qpart, cs, pend, ppart, rpart,
+                           nullptr, nullptr, 0, 0, 0, g.n_c, g.n_div, g.N, n_rhs);
+    else if (mode == RESTRICT_UPDATE)
+        hipLaunchKernelGGL((k_restrict3<M2, V2, NV, NC, RESTRICT_UPDATE, NR>), grid, block, lds, s, dsw,
+                           reinterpret_cast<const V2*>(w), reinterpret_cast<const V2*>(psi), nullptr,
+                           reinterpret_cast<V2*>(out), qpart, cs, pend, ppart, rpart, a, b, lda, ldb, step, g.n_c,
+                           g.n_div, g.N, n_rhs);
+    else
+        hipLaunchKernelGGL((k_restrict3<M2, V2, NV, NC, RESTRICT_INIT, NR>), grid, block, lds, s, dsw, nullptr, nullptr,
+                           reinterpret_cast<const double2*>(P), reinterpret_cast<V2*>(out), qpart, cs, pend, ppart,
+                           rpart, a, b, lda, ldb, 0, g.n_c, g.n_div, g.N, n_rhs);
+    return hipGetLastError();
+}
+
 template <class M2, class V2, int NV, int NC>
 hipError_t restrict_launch(const Plan& p, int mode, const void* x, const void* w, const void* psi, const double* P,
                            void* out, int step, double* a, double* b, int lda, int ldb, int n_rhs, hipStream_t s) {
@@ -493,21 +623,14 @@ hipError_t restrict_launch(const Plan& p, int mode, const void* x, const void* w
     dim3 grid(groups * 8 * n_rhs), block(kBlock);
     if (p.L.dsw_bytes > 0) {
         const M2* dsw = reinterpret_cast<const M2*>(p.ws + p.L.dsw);
-        const size_t lds = restrict_tile_lds(g);
-        if (mode == RESTRICT_PLAIN)
-            hipLaunchKernelGGL((k_restrict3<M2, V2, NV, NC, RESTRICT_PLAIN>), grid, block, lds, s, dsw,
-                               reinterpret_cast<const V2*>(x), nullptr, nullptr, nullptr, qpart, cs, pend, ppart,
-                               rpart, nullptr, nullptr, 0, 0, 0, g.n_c, g.n_div, g.N, n_rhs);
-        else if (mode == RESTRICT_UPDATE)
-            hipLaunchKernelGGL((k_restrict3<M2, V2, NV, NC, RESTRICT_UPDATE>), grid, block, lds, s, dsw,
-                               reinterpret_cast<const V2*>(w), reinterpret_cast<const V2*>(psi), nullptr,
-                               reinterpret_cast<V2*>(out), qpart, cs, pend, ppart, rpart, a, b, lda, ldb, step,
-                               g.n_c, g.n_div, g.N, n_rhs);
-        else
-            hipLaunchKernelGGL((k_restrict3<M2, V2, NV, NC, RESTRICT_INIT>), grid, block, lds, s, dsw, nullptr,
-                               nullptr, reinterpret_cast<const double2*>(P), reinterpret_cast<V2*>(out), qpart, cs,
-                               pend, ppart, rpart, a, b, lda, ldb, 0, g.n_c, g.n_div, g.N, n_rhs);
-        return hipGetLastError();
+        // right-hand sides per block: one (default), or all three when the plan asks
+        // for it and the tiles fit
+        if constexpr (NV * NC <= 18) {   // register budget of the three-rhs form
+            if (n_rhs == 3 && p.restrict_group == 3 && restrict3_lds(g, 3) <= 64 * 1024)
+                return restrict3_go<M2, V2, NV, NC, 3>(p, mode, dsw, x, w, psi, P, out, step, a, b, lda, ldb, n_rhs,
+                                                       s);
+        }
+        return restrict3_go<M2, V2, NV, NC, 1>(p, mode, dsw, x, w, psi, P, out, step, a, b, lda, ldb, n_rhs, s);
     }
     if (mode == RESTRICT_PLAIN)
         hipLaunchKernelGGL((k_restrict2<M2, V2, NV, NC, RESTRICT_PLAIN>), grid, block, 0, s, d,

@@ -133,6 +133,20 @@ def test_matvec_independent_of_product_splits(bse, splits):
     prob.close()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_restrict_group_gives_same_matvec(bse, dtype):
+    # one block per right-hand side, or one block for all three: same arithmetic per
+    # output, so the same bits
+    cfg = CASES[1]
+    prob = _problem(bse, cfg, dtype)
+    x = prob.vector(ti.random_vectors(prob.N, 3, 107))
+    y1 = prob.matvec(x).cpu().numpy()
+    bse.bse_plan_set_restrict_group(prob.plan, 3)
+    y3 = prob.matvec(x).cpu().numpy()
+    assert np.array_equal(y1, y3)
+    prob.close()
+
+
 def test_matvec_is_deterministic(bse):
     cfg = CASES[1]
     prob = _problem(bse, cfg, "f32")

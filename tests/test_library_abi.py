@@ -86,3 +86,4 @@ def test_other_entry_points_check_arguments(bse):
     m = bse.KernelModel(12.0, 0.3, 6.0, 4, 16)
     assert lib.bse_build_coarse_kernel(ctypes.byref(d_big), 1, 1, ctypes.byref(m), 1, None) == bse.BSE_ERR_UNSUPPORTED
     assert lib.bse_plan_set_gemv_splits(None, 4) == bse.BSE_ERR_INVALID_ARG
+    assert lib.bse_plan_set_restrict_group(None, 1) == bse.BSE_ERR_INVALID_ARG
