@@ -23,7 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_gemv2_restrict2_prolong2_c1_f32_hbm_counters.md")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "hbm_counters_c1_f32.md")
 GEMV_SOURCE = os.path.join(ROOT, "paper_1602_01863_amd", "csrc", "gemv.hip")
 
 
