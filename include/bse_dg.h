@@ -57,11 +57,26 @@ typedef enum {
 
 /* Storage precision of the coarse kernel, the overlaps and the Lanczos
  * vectors.  Every sum (restrict, coarse product, prolong, dot products) is
- * accumulated in FP64 whatever the storage. */
+ * accumulated in FP64 whatever the storage, except inside the matrix-core
+ * products of the two low-precision forms (see below).
+ *
+ * Low-precision forms (BSE_BF16_KC, BSE_F16_KC): the plan keeps K_c of Eq.
+ * (matmul2) as 64 x 64 blocks B with one FP32 scale s_B each (a power of two
+ * >= the block's largest real or imaginary part) and entries K / s_B in BF16 or
+ * FP16.  The coarse vector qbar enters the matrix-core product as a sum of two
+ * terms of the same format (its leading part and the remainder), so that K's
+ * rounding (unit roundoff 2^-8 for BF16; 2^-11 for FP16 above 2^-14 of the block
+ * scale, 2^-25 of the scale absolute below) dominates the error.  Products over one block accumulate in FP32 on the
+ * matrix cores; block results are scaled and added in FP64.  For FP16, qbar is
+ * multiplied by 2^9 before the conversion (and the product by 2^-9): this stays
+ * in range for vectors of norm <= 1, as in the Haydock chain.  The input K_c,
+ * the overlaps and the Lanczos vectors are complex FP32. */
 typedef enum {
-    BSE_F64 = 0,       /* kernel, overlaps, vectors: complex FP64 */
-    BSE_F32 = 1,       /* kernel, overlaps, vectors: complex FP32 */
-    BSE_F32_VEC64 = 2  /* kernel, overlaps: complex FP32; Lanczos vectors: complex FP64 */
+    BSE_F64 = 0,        /* kernel, overlaps, vectors: complex FP64 */
+    BSE_F32 = 1,        /* kernel, overlaps, vectors: complex FP32 */
+    BSE_F32_VEC64 = 2,  /* kernel, overlaps: complex FP32; Lanczos vectors: complex FP64 */
+    BSE_BF16_KC = 3,    /* kernel in block-scaled BF16 (from an FP32 input); rest FP32 */
+    BSE_F16_KC = 4      /* kernel in block-scaled FP16 (from an FP32 input); rest FP32 */
 } bse_dtype;
 
 typedef struct {
@@ -97,7 +112,8 @@ const char* bse_last_error(void);
  * The workspace must be 256-byte aligned. */
 size_t bse_workspace_bytes(const bse_dims* dims);
 
-/* Bytes of one coarse kernel (Nc x Nc complex) and of the overlap array for dims. */
+/* Bytes of one coarse kernel (Nc x Nc complex; FP32 for the low-precision forms,
+ * whose block-scaled copy lives in the plan's workspace) and of the overlap array. */
 size_t bse_coarse_kernel_bytes(const bse_dims* dims);
 size_t bse_overlaps_bytes(const bse_dims* dims);
 
@@ -155,9 +171,12 @@ bse_status bse_build_coarse_kernel(const bse_dims* dims, const double* vecs_coar
  *              initialisation; one plan must not run on two streams at once.
  *              Besides scratch space it holds the restrict tiles: a copy of d
  *              re-ordered for the restrict kernel, with the valence blocks already
- *              multiplied by the prefactors f (Sec. 3).
- *   stream     the copy is written by a kernel enqueued on this stream; later calls
- *              on the plan must be ordered after it (same stream, or synchronised).
+ *              multiplied by the prefactors f (Sec. 3); for BSE_BF16_KC and
+ *              BSE_F16_KC also the block-scaled copy of Kc (Kc itself is then not
+ *              read after plan creation).
+ *   stream     the copies are written by kernels enqueued on this stream; later
+ *              calls on the plan must be ordered after them (same stream, or
+ *              synchronised).
  */
 bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d,
                            const double* delta, void* workspace, size_t workspace_bytes,

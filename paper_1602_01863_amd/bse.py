@@ -30,8 +30,8 @@ BSE_ERR_NONFINITE = -3
 BSE_ERR_UNSUPPORTED = -4
 BSE_ERR_WORKSPACE = -5
 
-BSE_F64, BSE_F32, BSE_F32_VEC64 = 0, 1, 2
-DTYPES = {"f64": BSE_F64, "f32": BSE_F32, "f32v64": BSE_F32_VEC64}
+BSE_F64, BSE_F32, BSE_F32_VEC64, BSE_BF16_KC, BSE_F16_KC = 0, 1, 2, 3, 4
+DTYPES = {"f64": BSE_F64, "f32": BSE_F32, "f32v64": BSE_F32_VEC64, "bf16": BSE_BF16_KC, "f16": BSE_F16_KC}
 
 # symbols declared in include/bse_dg.h
 EXPORTED = [
@@ -205,7 +205,7 @@ def _storage(dtype_code: int):
     """(matrix complex dtype, vector complex dtype) for a bse_dtype."""
     if dtype_code == BSE_F64:
         return torch.complex128, torch.complex128
-    if dtype_code == BSE_F32:
+    if dtype_code in (BSE_F32, BSE_BF16_KC, BSE_F16_KC):
         return torch.complex64, torch.complex64
     return torch.complex64, torch.complex128
 

@@ -46,7 +46,8 @@ bool make_geometry(const bse_dims* d, Geometry* g) {
         set_error("max_rhs must be in [1, %d]", kMaxRhs);
         return false;
     }
-    if (d->dtype != BSE_F64 && d->dtype != BSE_F32 && d->dtype != BSE_F32_VEC64) {
+    if (d->dtype != BSE_F64 && d->dtype != BSE_F32 && d->dtype != BSE_F32_VEC64 && d->dtype != BSE_BF16_KC &&
+        d->dtype != BSE_F16_KC) {
         set_error("unknown dtype %d", d->dtype);
         return false;
     }
@@ -79,7 +80,21 @@ bool make_geometry(const bse_dims* d, Geometry* g) {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static constexpr int kWaveHost = 64;  // lanes of a wavefront (restrict tile width)
-static size_t vec_elem_bytes(int dtype) { return dtype == BSE_F32 ? sizeof(float2) : sizeof(double2); }
+
+size_t lds_limit() {
+    // shared memory one block may use on the current device (queried once per device)
+    static size_t cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 64 * 1024;
+    if (cache[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 64 * 1024;
+        cache[dev] = (size_t)v;
+    }
+    return cache[dev];
+}
+static size_t vec_elem_bytes(int dtype) { return vec_is_f32(dtype) ? sizeof(float2) : sizeof(double2); }
 static size_t mat_elem_bytes(int dtype) { return dtype == BSE_F64 ? sizeof(double2) : sizeof(float2); }
 
 Layout make_layout(const Geometry& g) {
@@ -101,6 +116,17 @@ Layout make_layout(const Geometry& g) {
     L.pend = take((size_t)kMaxRhs * sizeof(StepScalars));
     L.vec_a = take((size_t)g.N * R * vec_elem_bytes(g.dtype));
     L.vec_b = take((size_t)g.N * R * vec_elem_bytes(g.dtype));
+    L.kq = L.kscale = L.qfrag = off;
+    L.kq_bytes = L.kscale_bytes = L.qfrag_bytes = 0;
+    if (kc_lowp(g.dtype)) {
+        const KqShape k = kq_shape(g.Nc);
+        L.kq_bytes = (size_t)k.nb * k.nb * kKqBlock * kKqBlock * 4;
+        L.kscale_bytes = (size_t)k.nb * k.nb * sizeof(float);
+        L.qfrag_bytes = (size_t)k.nstep * 2 * kWaveHost * 16;
+        L.kq = take(L.kq_bytes);
+        L.kscale = take(L.kscale_bytes);
+        L.qfrag = take(L.qfrag_bytes);
+    }
     L.dsw_bytes = 0;
     L.dsw = off;
     if (supported_bands(g.nv, g.nc) && restrict_tile_lds(g) > 0) {
@@ -278,8 +304,10 @@ bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d, 
     p->ev_used = 0;
     p->timed_ms = 0.0;
     p->timed_launches = 0;
-    // restrict tiles: a re-ordered copy of the overlaps in the workspace
+    // restrict tiles: a re-ordered copy of the overlaps in the workspace; for the
+    // low-precision forms also the block-scaled coarse kernel
     hipError_t e = launch_swizzle(*p, stream);
+    if (e == hipSuccess) e = launch_quantize(*p, stream);
     if (e != hipSuccess) {
         delete p;
         return hip_fail(e, "bse_plan_create");

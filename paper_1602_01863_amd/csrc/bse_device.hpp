@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "bse_dg.h"
+
 namespace bse {
 
 constexpr int kWave = 64;
@@ -121,6 +123,16 @@ __device__ __forceinline__ double swap_pair_d(double v) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 __device__ __forceinline__ double2 swap_pair(double2 v) { return make_double2(swap_pair_d(v.x), swap_pair_d(v.y)); }
+
+// ---- 16-bit storage formats of the low-precision coarse kernel (BSE_BF16_KC,
+// BSE_F16_KC): round to nearest even from FP32, and back ----------------------------------
+__device__ __forceinline__ unsigned short enc_lowp(int fmt, float v) {
+    return fmt == BSE_BF16_KC ? __builtin_bit_cast(unsigned short, (__bf16)v)
+                              : __builtin_bit_cast(unsigned short, (_Float16)v);
+}
+__device__ __forceinline__ float dec_lowp(int fmt, unsigned short v) {
+    return fmt == BSE_BF16_KC ? (float)__builtin_bit_cast(__bf16, v) : (float)__builtin_bit_cast(_Float16, v);
+}
 
 // ---- interpolation prefactors (Sec. 3) ----------------------------------------------
 // f^l_j = 1 - j/n for l = 0 and j/n for l = 1, so the trilinear

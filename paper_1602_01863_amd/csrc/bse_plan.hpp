@@ -67,11 +67,30 @@ __host__ __device__ inline SwzShape swz_shape(int nv, int nc, int ndiv3, int ele
     return z;
 }
 
+// Low-precision coarse kernel (BSE_BF16_KC, BSE_F16_KC): 64 x 64 blocks, one FP32
+// scale each; the coarse index padded with zeros to a multiple of 64.  qbar enters the
+// matrix-core product as fragments for 32-column steps (see gemv.hip).
+constexpr int kKqBlock = 64;
+struct KqShape {
+    int nb;     // blocks per side: ceil(Nc / 64)
+    int nstep;  // 32-column steps: 2 nb
+};
+inline KqShape kq_shape(int64_t Nc) {
+    KqShape k;
+    k.nb = (int)((Nc + kKqBlock - 1) / kKqBlock);
+    k.nstep = 2 * k.nb;
+    return k;
+}
+inline bool kc_lowp(int dtype) { return dtype == BSE_BF16_KC || dtype == BSE_F16_KC; }
+// Lanczos vectors in FP32 storage
+inline bool vec_is_f32(int dtype) { return dtype == BSE_F32 || kc_lowp(dtype); }
+
 // workspace regions (byte offsets from the workspace base); dsw_bytes == 0 when the
-// restrict reads the overlaps in their input layout
+// restrict reads the overlaps in their input layout; kq, kscale, qfrag only for the
+// low-precision forms
 struct Layout {
-    size_t qpart, qbar, rvec, gpart, ppart, rpart, chain, pend, vec_a, vec_b, dsw;
-    size_t dsw_bytes;
+    size_t qpart, qbar, rvec, gpart, ppart, rpart, chain, pend, vec_a, vec_b, dsw, kq, kscale, qfrag;
+    size_t dsw_bytes, kq_bytes, kscale_bytes, qfrag_bytes;
     size_t total;
 };
 Layout make_layout(const Geometry& g);
@@ -108,6 +127,8 @@ bool supported_bands(int nv, int nc);
 
 // restrict tiles from the overlaps (restrict.hip), enqueued at plan creation
 hipError_t launch_swizzle(const Plan& p, hipStream_t s);
+// block-scaled coarse kernel and cleared qbar fragments (gemv.hip), at plan creation
+hipError_t launch_quantize(const Plan& p, hipStream_t s);
 // vector slice of a cell held in LDS by the tiled restrict: bytes, or 0 if it does not fit
 size_t restrict_tile_lds(const Geometry& g);
 
@@ -134,7 +155,7 @@ hipError_t prolong_launch(const Plan& p, int mode, const void* x, void* out, int
 __host__ __device__ inline int state_in(int step) { return step & 1; }
 __host__ __device__ inline int state_out(int step) { return (step + 1) & 1; }
 // breakdown threshold: b_{i+1} <= tol ||w||, by vector storage precision
-inline double breakdown_tol(int dtype) { return dtype == BSE_F32 ? 1e-6 : 1e-12; }
+inline double breakdown_tol(int dtype) { return vec_is_f32(dtype) ? 1e-6 : 1e-12; }
 
 // modes of the restrict launch
 enum { RESTRICT_PLAIN = 0, RESTRICT_UPDATE = 1, RESTRICT_INIT = 2 };
@@ -144,5 +165,7 @@ enum { COLLAPSE_PLAIN = 0, COLLAPSE_INIT = 1, COLLAPSE_STEP = 2 };
 enum { PROLONG_PLAIN = 0, PROLONG_LANCZOS = 1 };
 
 void set_error(const char* fmt, ...);
+// bytes of shared memory (static + dynamic) one block may use on the current device
+size_t lds_limit();
 
 }  // namespace bse

@@ -44,6 +44,7 @@ struct Gv<double2> {
 };
 
 constexpr int kGemvUnroll = 8;
+constexpr int kGemvLdsCols = 2048;  // qbar entries (double2) staged in LDS at a time: 32 KiB
 
 // lane l of a block owns rows base + l*E + e, e < E (one 16-byte load per column)
 template <class M2, int NRHS, bool FULL>
@@ -106,10 +107,6 @@ __global__ __launch_bounds__(256, 4) void k_gemv2(const M2* __restrict__ K, cons
     const int lane = threadIdx.x % kWave;
     const int c_begin = s * col_chunk;
     const int c_end = min(Nc, c_begin + col_chunk);
-    const int ncol = c_end - c_begin;
-
-    for (int i = threadIdx.x; i < ncol * NRHS; i += blockDim.x) smem[i] = qbar[(int64_t)c_begin * NRHS + i];
-    __syncthreads();
 
     const int row = rb * RW + lane * E;
     const int valid = max(0, min(E, Nc - row));
@@ -118,14 +115,20 @@ __global__ __launch_bounds__(256, 4) void k_gemv2(const M2* __restrict__ K, cons
     for (int e = 0; e < E; ++e)
 #pragma unroll
         for (int r = 0; r < NRHS; ++r) acc[e][r] = cmake(0.0, 0.0);
-    const M2* kp = K + (int64_t)c_begin * Nc;
-    if (VEC && (rb + 1) * RW <= Nc)
-        gemv_stream<M2, NRHS, true>(kp, smem, Nc, ncol, row, valid, wave, acc);
-    else if (valid > 0)
-        gemv_stream<M2, NRHS, false>(kp, smem, Nc, ncol, row, valid, wave, acc);
+    // the split's columns in LDS-sized pieces of qbar
+    for (int c0 = c_begin; c0 < c_end; c0 += kGemvLdsCols / NRHS) {
+        const int ncol = min(c_end - c0, kGemvLdsCols / NRHS);
+        for (int i = threadIdx.x; i < ncol * NRHS; i += blockDim.x) smem[i] = qbar[(int64_t)c0 * NRHS + i];
+        __syncthreads();
+        const M2* kp = K + (int64_t)c0 * Nc;
+        if (VEC && (rb + 1) * RW <= Nc)
+            gemv_stream<M2, NRHS, true>(kp, smem, Nc, ncol, row, valid, wave, acc);
+        else if (valid > 0)
+            gemv_stream<M2, NRHS, false>(kp, smem, Nc, ncol, row, valid, wave, acc);
+        __syncthreads();
+    }
 
     // cross-wave sum in fixed order (waves 1..3 into LDS, wave 0 adds)
-    __syncthreads();
     constexpr int PER = E * NRHS;
     double2* red = smem;  // 3 * 64 * PER entries
     if (wave > 0) {
@@ -198,7 +201,9 @@ static hipError_t gemv_t(Plan& p, hipStream_t s) {
     constexpr int RW = kWave * Gv<M2>::E;
     int n_rowblk, n_split, chunk;
     gemv_shape(p, RW, &n_rowblk, &n_split, &chunk);
-    const size_t lds = std::max((size_t)chunk * NRHS, (size_t)3 * kWave * Gv<M2>::E * NRHS) * sizeof(double2);
+    const size_t lds =
+        std::max((size_t)std::min(chunk, kGemvLdsCols / NRHS) * NRHS, (size_t)3 * kWave * Gv<M2>::E * NRHS) *
+        sizeof(double2);
     const bool vec = (g.Nc * (int64_t)sizeof(M2)) % 16 == 0;
     const M2* K = reinterpret_cast<const M2*>(p.Kc);
     const double2* qbar = reinterpret_cast<const double2*>(p.ws + p.L.qbar);
@@ -214,6 +219,212 @@ static hipError_t gemv_t(Plan& p, hipStream_t s) {
     const int64_t n_out = g.Nc * NRHS;
     hipLaunchKernelGGL(k_gemv_reduce, dim3((unsigned)((n_out + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, part, rvec,
                        n_out, n_split);
+    return hipGetLastError();
+}
+
+// ---- low-precision forms: block-scaled BF16 / FP16 coarse kernel on the matrix cores ----
+//
+// r = K_c qbar in real arithmetic: with K = Kr + i Ki and the coarse vectors split as
+// q = q_hi + q_lo (each part in the storage format),
+//   D = Kr [qr_hi qi_hi qr_lo qi_lo] + Ki [-qi_hi qr_hi -qi_lo qr_lo]
+// gives Re r = D[:, rhs] + D[:, 8 + rhs] and Im r = D[:, 4 + rhs] + D[:, 12 + rhs]
+// (16 columns: 4 right-hand sides x {re, im} x {hi, lo}).  One wavefront owns 16 rows
+// of a 64-row block row; per 64 x 64 block it issues four 16x16x32 matrix-core
+// products (two 32-column steps x {Kr, Ki}) into a fresh FP32 tile, then adds
+// scale x tile into FP64 accumulators.
+//
+// Operand layouts (16x16x32, 8 entries per lane): A[m][k] in lane 16 (k / 8) + m,
+// entry k % 8; B[k][n] in lane 16 (k / 8) + n, entry k % 8; D[m][n] in lane
+// 16 (m / 4) + n, entry m % 4.  The plan stores every block as 16 A fragments of
+// 1 KiB (fragment (rg, ks, part) = rows 16 rg.., columns 32 ks.., real or imaginary
+// part) and the collapse writes qbar as B fragments, two variants per 32-column step.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int FMT>
+struct Lowp;
+template <>
+struct Lowp<BSE_BF16_KC> {
+    static constexpr double qscale = 1.0;
+    __device__ static inline unsigned short enc(float v) { return enc_lowp(BSE_BF16_KC, v); }
+    __device__ static inline f32x4 mfma(u32x4 a, u32x4 b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                       0, 0, 0);
+    }
+};
+template <>
+struct Lowp<BSE_F16_KC> {
+    static constexpr double qscale = 512.0;  // qbar x 2^9 before the conversion
+    __device__ static inline unsigned short enc(float v) { return enc_lowp(BSE_F16_KC, v); }
+    __device__ static inline f32x4 mfma(u32x4 a, u32x4 b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                      0, 0, 0);
+    }
+};
+
+// block (bi, bj) of the padded coarse kernel: scale = smallest power of two >= the
+// largest |Re| or |Im| entry (1 for a zero block), entries K / scale in the format
+template <int FMT>
+__global__ __launch_bounds__(256) void k_quantize(const float2* __restrict__ K, unsigned short* __restrict__ kq,
+                                                  float* __restrict__ kscale, int64_t Nc, int nb) {
+    __shared__ float smax[kBlock / kWave];
+    const int bi = blockIdx.x / nb, bj = blockIdx.x % nb;
+    const int t = threadIdx.x;
+    constexpr int PER = kKqBlock * kKqBlock / kBlock;  // 16 entries per thread
+    float2 v[PER];
+    float mx = 0.0f;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = t + u * kBlock;
+        const int64_t row = (int64_t)bi * kKqBlock + e / kKqBlock, col = (int64_t)bj * kKqBlock + e % kKqBlock;
+        v[u] = (row < Nc && col < Nc) ? K[row * Nc + col] : make_float2(0.0f, 0.0f);
+        mx = fmaxf(mx, fmaxf(fabsf(v[u].x), fabsf(v[u].y)));
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, kWave));
+    if (t % kWave == 0) smax[t / kWave] = mx;
+    __syncthreads();
+    mx = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
+    int ex = 0;
+    if (mx > 0.0f) {
+        (void)frexpf(mx, &ex);          // mx = f 2^ex, f in [1/2, 1)
+        if (ldexpf(1.0f, ex - 1) >= mx) ex -= 1;  // exact powers of two map to themselves
+    }
+    const float sc = mx > 0.0f ? ldexpf(1.0f, ex) : 1.0f;
+    const float inv = 1.0f / sc;       // a power of two: exact
+    unsigned short* tile = kq + ((int64_t)bi * nb + bj) * (kKqBlock * kKqBlock * 2);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = t + u * kBlock;
+        const int row = e / kKqBlock, col = e % kKqBlock;
+        const int rg = row / 16, m = row % 16, ks = col / 32, kk = col % 32;
+        const int lane = (kk / 8) * 16 + m, ent = kk % 8;
+        const int fr_re = (rg * 2 + ks) * 2, fr_im = fr_re + 1;
+        tile[(fr_re * kWave + lane) * 8 + ent] = Lowp<FMT>::enc(v[u].x * inv);
+        tile[(fr_im * kWave + lane) * 8 + ent] = Lowp<FMT>::enc(v[u].y * inv);
+    }
+    if (t == 0) kscale[(int64_t)bi * nb + bj] = sc;
+}
+
+__global__ void k_zero_u32(unsigned int* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_quantize(const Plan& p, hipStream_t s) {
+    const Geometry& g = p.g;
+    if (!kc_lowp(g.dtype)) return hipSuccess;
+    const KqShape k = kq_shape(g.Nc);
+    unsigned short* kq = reinterpret_cast<unsigned short*>(p.ws + p.L.kq);
+    float* ksc = reinterpret_cast<float*>(p.ws + p.L.kscale);
+    const float2* K = reinterpret_cast<const float2*>(p.Kc);
+    if (g.dtype == BSE_BF16_KC)
+        hipLaunchKernelGGL(k_quantize<BSE_BF16_KC>, dim3((unsigned)(k.nb * k.nb)), dim3(kBlock), 0, s, K, kq, ksc, g.Nc,
+                           k.nb);
+    else
+        hipLaunchKernelGGL(k_quantize<BSE_F16_KC>, dim3((unsigned)(k.nb * k.nb)), dim3(kBlock), 0, s, K, kq, ksc, g.Nc,
+                           k.nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nw = (int64_t)(p.L.qfrag_bytes / 4);
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((nw + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       reinterpret_cast<unsigned int*>(p.ws + p.L.qfrag), nw);
+    return hipGetLastError();
+}
+
+constexpr int kMfmaUnroll = 2;  // 64-column blocks whose operands are in flight together
+
+template <int FMT>
+__global__ __launch_bounds__(256) void k_gemv_mfma(const u32x4* __restrict__ kq, const float* __restrict__ kscale,
+                                                   const u32x4* __restrict__ qf, double* __restrict__ part, int Nc,
+                                                   int nb, int cpb, int n_rhs) {
+    const int bi = blockIdx.x % nb;
+    const int sp = blockIdx.x / nb;
+    const int rg = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int bj0 = sp * cpb, bj1 = min(nb, bj0 + cpb);
+    // this wavefront's 4 A fragments of block (bi, bj): (ks, part) = (0, re), (0, im), (1, re), (1, im)
+    const u32x4* arow = kq + (int64_t)bi * nb * 16 * kWave + (rg * 4) * kWave + lane;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const double qinv = 1.0 / Lowp<FMT>::qscale;
+    int bj = bj0;
+    for (; bj + kMfmaUnroll <= bj1; bj += kMfmaUnroll) {
+        u32x4 a[kMfmaUnroll][4], b[kMfmaUnroll][4];
+        float sc[kMfmaUnroll];
+#pragma unroll
+        for (int u = 0; u < kMfmaUnroll; ++u) {
+            const u32x4* ab = arow + (int64_t)(bj + u) * 16 * kWave;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) a[u][f] = __builtin_nontemporal_load(ab + f * kWave);
+            // B fragments of the block's two 32-column steps: (step, variant)
+#pragma unroll
+            for (int f = 0; f < 4; ++f) b[u][f] = qf[((int64_t)(2 * (bj + u) + (f >> 1)) * 2 + (f & 1)) * kWave + lane];
+            sc[u] = kscale[(int64_t)bi * nb + bj + u];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < kMfmaUnroll; ++u) {
+            f32x4 d = {0.0f, 0.0f, 0.0f, 0.0f};
+            d = Lowp<FMT>::mfma(a[u][0], b[u][0], d);  // Kr x B1, first 32 columns
+            d = Lowp<FMT>::mfma(a[u][1], b[u][1], d);  // Ki x B2
+            d = Lowp<FMT>::mfma(a[u][2], b[u][2], d);  // second 32 columns
+            d = Lowp<FMT>::mfma(a[u][3], b[u][3], d);
+            const double w = (double)sc[u] * qinv;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] = fma(w, (double)d[e], acc[e]);
+        }
+    }
+    for (; bj < bj1; ++bj) {
+        const u32x4* ab = arow + (int64_t)bj * 16 * kWave;
+        f32x4 d = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+            d = Lowp<FMT>::mfma(ab[f * kWave], qf[((int64_t)(2 * bj + (f >> 1)) * 2 + (f & 1)) * kWave + lane], d);
+        const double w = (double)kscale[(int64_t)bi * nb + bj] * qinv;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = fma(w, (double)d[e], acc[e]);
+    }
+    // column n = lane % 16 holds (hi, lo) parts in n and n + 8: add them; rows 4 (lane / 16) + e
+    const int n = lane % 16;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[e] += __shfl_xor(acc[e], 8, kWave);
+    if (n < 8) {
+        const int r = n & 3, comp = n >> 2;  // n = r: real part, n = 4 + r: imaginary part
+        if (r < n_rhs) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = bi * kKqBlock + rg * 16 + 4 * (lane / 16) + e;
+                if (row < Nc) part[(((int64_t)sp * Nc + row) * n_rhs + r) * 2 + comp] = acc[e];
+            }
+        }
+    }
+}
+
+static hipError_t gemv_lowp(Plan& p, int n_rhs, hipStream_t s) {
+    const Geometry& g = p.g;
+    const KqShape k = kq_shape(g.Nc);
+    int ns = p.n_split;
+    if (ns <= 0) ns = (2048 + k.nb - 1) / k.nb;
+    ns = std::max(1, std::min(std::min(ns, kMaxSplit), k.nb));
+    const int cpb = (k.nb + ns - 1) / ns;
+    ns = (k.nb + cpb - 1) / cpb;
+    const u32x4* kq = reinterpret_cast<const u32x4*>(p.ws + p.L.kq);
+    const float* ksc = reinterpret_cast<const float*>(p.ws + p.L.kscale);
+    const u32x4* qf = reinterpret_cast<const u32x4*>(p.ws + p.L.qfrag);
+    double* part = reinterpret_cast<double*>(p.ws + p.L.gpart);
+    double2* rvec = reinterpret_cast<double2*>(p.ws + p.L.rvec);
+    dim3 grid((unsigned)(k.nb * ns)), block(kBlock);
+    if (g.dtype == BSE_BF16_KC)
+        hipLaunchKernelGGL(k_gemv_mfma<BSE_BF16_KC>, grid, block, 0, s, kq, ksc, qf, part, (int)g.Nc, k.nb, cpb, n_rhs);
+    else
+        hipLaunchKernelGGL(k_gemv_mfma<BSE_F16_KC>, grid, block, 0, s, kq, ksc, qf, part, (int)g.Nc, k.nb, cpb, n_rhs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n_out = g.Nc * n_rhs;
+    hipLaunchKernelGGL(k_gemv_reduce, dim3((unsigned)((n_out + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       reinterpret_cast<const double2*>(part), rvec, n_out, ns);
     return hipGetLastError();
 }
 
@@ -235,7 +446,9 @@ hipError_t launch_gemv(Plan& p, int n_rhs, hipStream_t s) {
         p.ev_used += 2;
         (void)hipEventRecord(e0, s);
     }
-    hipError_t err = (p.g.dtype == BSE_F64) ? gemv_r<double2>(p, n_rhs, s) : gemv_r<float2>(p, n_rhs, s);
+    hipError_t err = kc_lowp(p.g.dtype)        ? gemv_lowp(p, n_rhs, s)
+                     : (p.g.dtype == BSE_F64) ? gemv_r<double2>(p, n_rhs, s)
+                                              : gemv_r<float2>(p, n_rhs, s);
     if (e1) (void)hipEventRecord(e1, s);
     return err;
 }

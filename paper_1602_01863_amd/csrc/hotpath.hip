@@ -41,7 +41,8 @@ __global__ __launch_bounds__(256) void k_collapse(const double2* __restrict__ qp
                                                   const StepScalars* __restrict__ pend,
                                                   const double* __restrict__ rpart, ChainState* __restrict__ cs_out,
                                                   double* __restrict__ beta, int ldb, int step, double tol2,
-                                                  int n_c, int np, int n_rhs, int64_t total) {
+                                                  int n_c, int np, int n_rhs, int64_t total,
+                                                  unsigned short* __restrict__ qfrag, int qfmt) {
     __shared__ double sred[2 * kMaxRhs][kBlock / kWave];
     __shared__ double sscale[kMaxRhs];
     const int ncells = n_c * n_c * n_c;
@@ -154,6 +155,29 @@ __global__ __launch_bounds__(256) void k_collapse(const double2* __restrict__ qp
     }
     const double sc = (MODE == COLLAPSE_PLAIN) ? 1.0 : sscale[r0];   // psi = s u in a chain
     qbar[i] = make_double2(sc * re, sc * im);
+    if (qfmt != 0) {
+        // low-precision forms: qbar as matrix-core B fragments (see gemv.hip), leading
+        // part and remainder in the storage format, two variants per 32-column step
+        const double qs = qfmt == BSE_F16_KC ? 512.0 : 1.0;
+        const double vr = sc * re * qs, vi = sc * im * qs;
+        const unsigned short hr = enc_lowp(qfmt, (float)vr), hi = enc_lowp(qfmt, (float)vi);
+        const unsigned short lr = enc_lowp(qfmt, (float)(vr - (double)dec_lowp(qfmt, hr)));
+        const unsigned short li = enc_lowp(qfmt, (float)(vi - (double)dec_lowp(qfmt, hi)));
+        const int64_t j = T;  // column of K_c
+        const int64_t g = j / 32;
+        const int kk = (int)(j % 32), lg = kk / 8, ent = kk % 8;
+        unsigned short* b1 = qfrag + ((g * 2 + 0) * kWave + lg * 16) * 8 + ent;
+        unsigned short* b2 = qfrag + ((g * 2 + 1) * kWave + lg * 16) * 8 + ent;
+        const unsigned short sign = 0x8000;
+        b1[(r0) * 8] = hr;
+        b1[(4 + r0) * 8] = hi;
+        b1[(8 + r0) * 8] = lr;
+        b1[(12 + r0) * 8] = li;
+        b2[(r0) * 8] = hi ^ sign;
+        b2[(4 + r0) * 8] = hr;
+        b2[(8 + r0) * 8] = li ^ sign;
+        b2[(12 + r0) * 8] = lr;
+    }
 }
 
 __global__ void k_chain_report(const ChainState* __restrict__ chain, double* pnorm2, int32_t* steps,
@@ -185,6 +209,8 @@ static hipError_t restrict_dt(const Plan& p, int mode, const void* x, const void
         case BSE_F64:
             return restrict_launch<double2, double2, NV, NC>(p, mode, x, w, psi, P, out, step, a, b, lda, ldb, n_rhs, s);
         case BSE_F32:
+        case BSE_BF16_KC:
+        case BSE_F16_KC:
             return restrict_launch<float2, float2, NV, NC>(p, mode, x, w, psi, P, out, step, a, b, lda, ldb, n_rhs, s);
         default:
             return restrict_launch<float2, double2, NV, NC>(p, mode, x, w, psi, P, out, step, a, b, lda, ldb, n_rhs, s);
@@ -196,7 +222,9 @@ static hipError_t prolong_dt(const Plan& p, int mode, const void* x, void* out, 
                              hipStream_t s) {
     switch (p.g.dtype) {
         case BSE_F64: return prolong_launch<double2, double2, NV, NC>(p, mode, x, out, step, n_rhs, s);
-        case BSE_F32: return prolong_launch<float2, float2, NV, NC>(p, mode, x, out, step, n_rhs, s);
+        case BSE_F32:
+        case BSE_BF16_KC:
+        case BSE_F16_KC: return prolong_launch<float2, float2, NV, NC>(p, mode, x, out, step, n_rhs, s);
         default: return prolong_launch<float2, double2, NV, NC>(p, mode, x, out, step, n_rhs, s);
     }
 }
@@ -231,18 +259,20 @@ hipError_t launch_collapse(const Plan& p, int mode, int step, double* b, int ldb
     const StepScalars* pend = reinterpret_cast<const StepScalars*>(p.ws + p.L.pend);
     const double* rpart = reinterpret_cast<const double*>(p.ws + p.L.rpart);
     const double tol = breakdown_tol(g.dtype);
+    unsigned short* qf = kc_lowp(g.dtype) ? reinterpret_cast<unsigned short*>(p.ws + p.L.qfrag) : nullptr;
+    const int qfmt = kc_lowp(g.dtype) ? g.dtype : 0;
     // the chain start writes copy 0, step i reads copy i % 2 and writes copy (i + 1) % 2
     const ChainState* cin = cs + state_in(step) * kMaxRhs;
     ChainState* cout = (mode == COLLAPSE_INIT) ? cs : cs + state_out(step) * kMaxRhs;
     if (mode == COLLAPSE_PLAIN)
         hipLaunchKernelGGL(k_collapse<COLLAPSE_PLAIN>, dim3(nb), dim3(kBlock), 0, s, qpart, qbar, cin, pend, rpart,
-                           cout, b, ldb, step, tol * tol, g.n_c, g.np, n_rhs, total);
+                           cout, b, ldb, step, tol * tol, g.n_c, g.np, n_rhs, total, qf, qfmt);
     else if (mode == COLLAPSE_INIT)
         hipLaunchKernelGGL(k_collapse<COLLAPSE_INIT>, dim3(nb), dim3(kBlock), 0, s, qpart, qbar, cin, pend, rpart,
-                           cout, b, ldb, step, tol * tol, g.n_c, g.np, n_rhs, total);
+                           cout, b, ldb, step, tol * tol, g.n_c, g.np, n_rhs, total, qf, qfmt);
     else
         hipLaunchKernelGGL(k_collapse<COLLAPSE_STEP>, dim3(nb), dim3(kBlock), 0, s, qpart, qbar, cin, pend, rpart,
-                           cout, b, ldb, step, tol * tol, g.n_c, g.np, n_rhs, total);
+                           cout, b, ldb, step, tol * tol, g.n_c, g.np, n_rhs, total, qf, qfmt);
     return hipGetLastError();
 }
 

@@ -358,7 +358,8 @@ hipError_t prolong_launch(const Plan& p, int mode, const void* x, void* out, int
     const size_t lds = prolong3_lds(NE, g.ndiv3, NP, n_rhs, sizeof(M2));
     // staged form: whole 16-byte units per (cell, corner) block and an aligned base
     const bool units = ((size_t)NE * g.ndiv3 * sizeof(M2)) % 16 == 0 && ((uintptr_t)p.d & 15) == 0;
-    if (g.ndiv3 <= kWave && lds <= 64 * 1024 && units) {
+    const size_t static_lds = 8 * kWave * sizeof(double) + kMaxRhs * 4 * sizeof(double);  // prefactors, partials
+    if (g.ndiv3 <= kWave && lds + static_lds <= lds_limit() && units) {
         switch (n_rhs) {
             case 1: prolong3_go<M2, V2, NV, NC, 1>(p, mode, xv, ov, cs, lds, s); break;
             case 2: prolong3_go<M2, V2, NV, NC, 2>(p, mode, xv, ov, cs, lds, s); break;

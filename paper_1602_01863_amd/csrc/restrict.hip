@@ -552,14 +552,15 @@ __global__ __launch_bounds__(256, (NR == 1 && sizeof(M2) == 8 && NV * NC <= 18) 
 }
 
 static size_t restrict3_lds(const Geometry& g, int nr) {
-    const size_t vb = g.dtype == BSE_F32 ? sizeof(float2) : sizeof(double2);
+    const size_t vb = vec_is_f32(g.dtype) ? sizeof(float2) : sizeof(double2);
     const size_t xs = (size_t)nr * 4 * ((g.ndiv3 + 3) / 4) * g.np * vb;
     return (xs + 15) / 16 * 16 + (size_t)(kBlock / kWave) * nr * 8 * g.np * sizeof(double2);
 }
 
 size_t restrict_tile_lds(const Geometry& g) {
     const size_t bytes = restrict3_lds(g, 1);
-    return bytes <= 64 * 1024 ? bytes : 0;
+    // fixed limit (not the device's): the workspace layout must not depend on the device
+    return bytes + 512 <= 64 * 1024 ? bytes : 0;   // 512: the block's static partials
 }
 
 hipError_t launch_swizzle(const Plan& p, hipStream_t s) {
@@ -590,7 +591,7 @@ static hipError_t restrict3_go(const Plan& p, int mode, const M2* dsw, const voi
     const double* ppart = reinterpret_cast<const double*>(p.ws + p.L.ppart);
     double* rpart = reinterpret_cast<double*>(p.ws + p.L.rpart);
     const size_t lds = restrict3_lds(g, NR);
-    if (lds > 64 * 1024 || n_rhs % NR != 0) return hipErrorInvalidConfiguration;
+    if (lds + 512 > lds_limit() || n_rhs % NR != 0) return hipErrorInvalidConfiguration;
     const int groups = (g.ncells + 7) / 8;
     dim3 grid(groups * 8 * (n_rhs / NR)), block(kBlock);
     if (mode == RESTRICT_PLAIN)
@@ -626,7 +627,7 @@ hipError_t restrict_launch(const Plan& p, int mode, const void* x, const void* w
         // right-hand sides per block: one (default), or all three when the plan asks
         // for it and the tiles fit
         if constexpr (NV * NC <= 18) {   // register budget of the three-rhs form
-            if (n_rhs == 3 && p.restrict_group == 3 && restrict3_lds(g, 3) <= 64 * 1024)
+            if (n_rhs == 3 && p.restrict_group == 3 && restrict3_lds(g, 3) + 512 <= lds_limit())
                 return restrict3_go<M2, V2, NV, NC, 3>(p, mode, dsw, x, w, psi, P, out, step, a, b, lda, ldb, n_rhs,
                                                        s);
         }
