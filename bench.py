@@ -51,7 +51,7 @@ def _args():
     p.add_argument("--steps", type=int, default=300)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--config", default="c1")
-    p.add_argument("--dtype", default=None, help="f32 | f32v64 | f64 (default: workload's)")
+    p.add_argument("--dtype", default=None, help="f32 | f32v64 | f64 | bf16 | f16 (default: workload's)")
     p.add_argument("--splits", type=int, default=0, help="column splits of the coarse product (0 = auto)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=8, help="oracle steps timed for the CPU baseline")
@@ -110,10 +110,19 @@ def main():
     prob.set_timing(False)
     gemv_ms = gemv_ms_total / max(1, gemv_launches)
     Nc, n_rhs = prob.Nc, cfg.n_pol
-    mat_bytes = 8 if dtype in ("f32", "f32v64") else 16
-    gemv_bytes = Nc * Nc * mat_bytes + 2 * Nc * n_rhs * 16      # K_c once + qbar in + r out
+    lowp = dtype in ("bf16", "f16")
+    mat_bytes = {"f64": 16, "f32": 8, "f32v64": 8, "bf16": 4, "f16": 4}[dtype]
+    nbk = -(-Nc // 64)
+    if lowp:   # 64 x 64 blocks in the format (zero-padded) + one FP32 scale per block
+        kc_bytes = nbk * nbk * 64 * 64 * mat_bytes + nbk * nbk * 4
+    else:
+        kc_bytes = Nc * Nc * mat_bytes
+    gemv_bytes = kc_bytes + 2 * Nc * n_rhs * 16                  # K_c once + qbar in + r out
     gemv_flops = 8.0 * Nc * Nc * n_rhs                           # complex MAC = 8 flops
     achieved_gbs = gemv_bytes / (gemv_ms * 1e-3) / 1e9
+    # matrix-core work actually issued: per 64 x 64 block and 16-row group, four 16x16x32
+    # products (16 columns: 4 rhs x re/im x leading/remainder)
+    mfma_flops = (nbk * 4) * nbk * 4 * (2.0 * 16 * 16 * 32) if lowp else 0.0
 
     # ---- time to eps2 on the host from a ready plan (chain + continued fraction + copy)
     om = cfg.omega()
@@ -135,8 +144,8 @@ def main():
     # ---- algorithmic bytes of a whole step (for the step-level bandwidth)
     N, ncell, ndiv3 = prob.N, cfg.nk_coarse, cfg.n_div3
     ne = cfg.nv ** 2 + cfg.nc ** 2
-    vec_bytes = 8 if dtype == "f32" else 16
-    d_bytes = ncell * 8 * ne * ndiv3 * mat_bytes
+    vec_bytes = 8 if dtype in ("f32", "bf16", "f16") else 16
+    d_bytes = ncell * 8 * ne * ndiv3 * (16 if dtype == "f64" else 8)
     step_bytes = (gemv_bytes + 2 * d_bytes                    # K_c; overlaps in prolong and restrict
                   + n_rhs * N * vec_bytes * 6                  # psi_i x2, psi_{i-1}, w write/read, u write
                   + N * 8)                                     # transition energies (FP64)
@@ -151,7 +160,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if dtype == "f32" else ("f32/f64-vectors" if dtype == "f32v64" else "f64"),
+        "dtype": {"f32": "f32", "f32v64": "f32/f64-vectors", "f64": "f64", "bf16": "bf16-kernel/f32",
+                  "f16": "f16-kernel/f32"}[dtype],
         "data": "synthetic (seeded tight-binding crystal)",
         "config": {
             "workload": (f"{cfg.name}: {cfg.n_coarse}^3 coarse x {cfg.n_div}^3 divisions "
@@ -166,10 +176,14 @@ def main():
         "coarse_product": {
             "avg_ms": round(gemv_ms, 5), "launches": gemv_launches,
             "TFLOPs": round(gemv_flops / (gemv_ms * 1e-3) / 1e12, 3),
-            "engine": "VALU FP64 FMA on FP32 storage (HBM-bound; no MFMA)",
+            "engine": ("matrix cores 16x16x32 " + dtype + ", FP32 in-block accumulation (HBM-bound)") if lowp
+            else "VALU FP64 FMA on " + ("FP64" if dtype == "f64" else "FP32") + " storage (HBM-bound; no MFMA)",
+            "MFMA_TFLOPs_issued": round(mfma_flops / (gemv_ms * 1e-3) / 1e12, 3) if lowp else None,
+            "MFMA_peak_TFLOPs": 2500.0 if lowp else None,
         },
         "roofline": {
-            "kernel": "coarse product r = K_c qbar (k_gemv2 + k_gemv_reduce)",
+            "kernel": ("coarse product r = K_c qbar (k_gemv_mfma + k_gemv_reduce)" if lowp
+                       else "coarse product r = K_c qbar (k_gemv2 + k_gemv_reduce)"),
             "bound": "hbm",
             "achieved": round(achieved_gbs, 1),
             "peak": HBM_PEAK_GBS,

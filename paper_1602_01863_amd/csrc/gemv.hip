@@ -95,7 +95,30 @@ __device__ __forceinline__ void gemv_stream(const M2* __restrict__ kp, const dou
     }
 }
 
-template <class M2, int NRHS, bool VEC>
+// MULTI: the split's columns do not fit in LDS at once and are staged in pieces
+template <class M2, int NRHS, bool FULL, bool MULTI>
+__device__ __forceinline__ void gemv_pieces(const M2* __restrict__ K, const double2* __restrict__ qbar, double2* smem,
+                                            int Nc, int c_begin, int c_end, int row, int valid, int wave,
+                                            cd (&acc)[Gv<M2>::E][NRHS]) {
+    if (!MULTI) {
+        const int ncol = c_end - c_begin;
+        for (int i = threadIdx.x; i < ncol * NRHS; i += blockDim.x) smem[i] = qbar[(int64_t)c_begin * NRHS + i];
+        __syncthreads();
+        if (FULL || valid > 0)
+            gemv_stream<M2, NRHS, FULL>(K + (int64_t)c_begin * Nc, smem, Nc, ncol, row, valid, wave, acc);
+        __syncthreads();
+        return;
+    }
+    for (int c0 = c_begin; c0 < c_end; c0 += kGemvLdsCols / NRHS) {
+        const int ncol = min(c_end - c0, kGemvLdsCols / NRHS);
+        for (int i = threadIdx.x; i < ncol * NRHS; i += blockDim.x) smem[i] = qbar[(int64_t)c0 * NRHS + i];
+        __syncthreads();
+        if (FULL || valid > 0) gemv_stream<M2, NRHS, FULL>(K + (int64_t)c0 * Nc, smem, Nc, ncol, row, valid, wave, acc);
+        __syncthreads();
+    }
+}
+
+template <class M2, int NRHS, bool VEC, bool MULTI>
 __global__ __launch_bounds__(256, 4) void k_gemv2(const M2* __restrict__ K, const double2* __restrict__ qbar,
                                                   double2* __restrict__ part, int Nc, int col_chunk, int n_rowblk) {
     constexpr int E = Gv<M2>::E;
@@ -116,17 +139,10 @@ __global__ __launch_bounds__(256, 4) void k_gemv2(const M2* __restrict__ K, cons
 #pragma unroll
         for (int r = 0; r < NRHS; ++r) acc[e][r] = cmake(0.0, 0.0);
     // the split's columns in LDS-sized pieces of qbar
-    for (int c0 = c_begin; c0 < c_end; c0 += kGemvLdsCols / NRHS) {
-        const int ncol = min(c_end - c0, kGemvLdsCols / NRHS);
-        for (int i = threadIdx.x; i < ncol * NRHS; i += blockDim.x) smem[i] = qbar[(int64_t)c0 * NRHS + i];
-        __syncthreads();
-        const M2* kp = K + (int64_t)c0 * Nc;
-        if (VEC && (rb + 1) * RW <= Nc)
-            gemv_stream<M2, NRHS, true>(kp, smem, Nc, ncol, row, valid, wave, acc);
-        else if (valid > 0)
-            gemv_stream<M2, NRHS, false>(kp, smem, Nc, ncol, row, valid, wave, acc);
-        __syncthreads();
-    }
+    if (VEC && (rb + 1) * RW <= Nc)
+        gemv_pieces<M2, NRHS, true, MULTI>(K, qbar, smem, Nc, c_begin, c_end, row, valid, wave, acc);
+    else
+        gemv_pieces<M2, NRHS, false, MULTI>(K, qbar, smem, Nc, c_begin, c_end, row, valid, wave, acc);
 
     // cross-wave sum in fixed order (waves 1..3 into LDS, wave 0 adds)
     constexpr int PER = E * NRHS;
@@ -210,10 +226,19 @@ static hipError_t gemv_t(Plan& p, hipStream_t s) {
     double2* part = reinterpret_cast<double2*>(p.ws + p.L.gpart);
     double2* rvec = reinterpret_cast<double2*>(p.ws + p.L.rvec);
     dim3 grid(n_rowblk * n_split), block(kBlock);
-    if (vec)
-        hipLaunchKernelGGL((k_gemv2<M2, NRHS, true>), grid, block, lds, s, K, qbar, part, (int)g.Nc, chunk, n_rowblk);
+    const bool multi = chunk > kGemvLdsCols / NRHS;
+    if (vec && !multi)
+        hipLaunchKernelGGL((k_gemv2<M2, NRHS, true, false>), grid, block, lds, s, K, qbar, part, (int)g.Nc, chunk,
+                           n_rowblk);
+    else if (vec)
+        hipLaunchKernelGGL((k_gemv2<M2, NRHS, true, true>), grid, block, lds, s, K, qbar, part, (int)g.Nc, chunk,
+                           n_rowblk);
+    else if (!multi)
+        hipLaunchKernelGGL((k_gemv2<M2, NRHS, false, false>), grid, block, lds, s, K, qbar, part, (int)g.Nc, chunk,
+                           n_rowblk);
     else
-        hipLaunchKernelGGL((k_gemv2<M2, NRHS, false>), grid, block, lds, s, K, qbar, part, (int)g.Nc, chunk, n_rowblk);
+        hipLaunchKernelGGL((k_gemv2<M2, NRHS, false, true>), grid, block, lds, s, K, qbar, part, (int)g.Nc, chunk,
+                           n_rowblk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t n_out = g.Nc * NRHS;
