@@ -233,6 +233,29 @@ bse_status bse_continued_fraction(const double* a, const double* b, int32_t lda,
 bse_status bse_plan_set_timing(bse_plan* plan, int32_t enable);
 bse_status bse_plan_get_timing(bse_plan* plan, double* total_ms, int64_t* launches);
 
+/*
+ * Batched chains: one Haydock run (Eqs. ai-ci, as bse_haydock_run with n_steps
+ * steps) per plan, for many plans of any sizes, recorded once into HIP graphs and
+ * submitted by a single call.  Plan i starts from P[i] (n_rhs[i] right-hand
+ * sides) and writes a[i], b[i], pnorm2[i], steps_done[i], status[i] with the
+ * layouts of bse_haydock_run.  The runs are dealt to n_branches (1..16) branches,
+ * largest first; each branch is recorded once into its own HIP graph.  A launch
+ * forks `stream` onto the batch's own streams (default priority), launches every
+ * branch's graph there and joins back into `stream`, so small Hamiltonians run
+ * beside large ones.  All pointers are recorded in the graphs: they, the plans and
+ * their inputs must stay valid and unchanged until bse_batch_destroy, which must
+ * come after the last launch has completed; a plan may appear once, must have
+ * kernel timing disabled, and must not be used elsewhere while a launch runs.
+ * Every launch recomputes all chains from their starts.
+ */
+typedef struct bse_batch bse_batch;
+bse_status bse_batch_create(bse_plan* const* plans, int32_t n_plans, const double* const* P,
+                            const int32_t* n_rhs, int32_t n_steps, double* const* a,
+                            double* const* b, double* const* pnorm2, int32_t* const* steps_done,
+                            int32_t* const* status, int32_t n_branches, bse_batch** batch_out);
+bse_status bse_batch_launch(bse_batch* batch, hipStream_t stream);
+void bse_batch_destroy(bse_batch* batch);
+
 /* Tunables of the coarse product: column splits (0 = automatic).  For sweeps. */
 bse_status bse_plan_set_gemv_splits(bse_plan* plan, int32_t n_split);
 

@@ -39,7 +39,8 @@ EXPORTED = [
     "bse_overlaps_bytes", "bse_build_overlaps", "bse_build_transition_energies",
     "bse_build_coarse_kernel", "bse_plan_create", "bse_plan_destroy", "bse_interp_matvec",
     "bse_haydock_run", "bse_continued_fraction", "bse_plan_set_timing", "bse_plan_get_timing",
-    "bse_plan_set_gemv_splits", "bse_plan_set_restrict_group",
+    "bse_plan_set_gemv_splits", "bse_plan_set_restrict_group", "bse_batch_create", "bse_batch_launch",
+    "bse_batch_destroy",
 ]
 
 
@@ -83,6 +84,9 @@ def _load():
         "bse_plan_get_timing": (i32, [vp, P(dbl), P(i64)]),
         "bse_plan_set_gemv_splits": (i32, [vp, i32]),
         "bse_plan_set_restrict_group": (i32, [vp, i32]),
+        "bse_batch_create": (i32, [P(vp), i32, P(vp), P(i32), i32, P(vp), P(vp), P(vp), P(vp), P(vp), i32, P(vp)]),
+        "bse_batch_launch": (i32, [vp, vp]),
+        "bse_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -198,6 +202,75 @@ def bse_plan_set_gemv_splits(plan, n_split: int):
 
 def bse_plan_set_restrict_group(plan, rhs_per_block: int):
     _check(_lib.bse_plan_set_restrict_group(plan, int(rhs_per_block)), "bse_plan_set_restrict_group")
+
+
+def bse_batch_create(plans, P_list, n_rhs, n_steps, a, b, pnorm2, steps_done, status, n_branches):
+    n = len(plans)
+    arr = lambda cls, xs: (cls * n)(*xs)
+    vp = ctypes.c_void_p
+    batch = ctypes.c_void_p()
+    _check(_lib.bse_batch_create(arr(vp, plans), n, arr(vp, [_ptr(t) for t in P_list]),
+                                 arr(ctypes.c_int32, [int(r) for r in n_rhs]), int(n_steps),
+                                 arr(vp, [_ptr(t) for t in a]), arr(vp, [_ptr(t) for t in b]),
+                                 arr(vp, [_ptr(t) for t in pnorm2]), arr(vp, [_ptr(t) for t in steps_done]),
+                                 arr(vp, [_ptr(t) for t in status]), int(n_branches), ctypes.byref(batch)),
+           "bse_batch_create")
+    return batch
+
+
+def bse_batch_launch(batch, stream=None):
+    _check(_lib.bse_batch_launch(batch, _stream(stream)), "bse_batch_launch")
+
+
+def bse_batch_destroy(batch):
+    _lib.bse_batch_destroy(batch)
+
+
+class BSEBatch:
+    """Haydock chains of many problems recorded into HIP graphs, one per branch (bse_batch_*).
+
+    problems: BSEProblem list; P_list: matching [n_rhs, N] start vectors.  The output
+    tensors are allocated here and stay attached to the graph; every run() recomputes
+    all chains and leaves them in .chains (one dict per problem, as BSEProblem.haydock).
+    """
+
+    def __init__(self, problems, P_list, n_steps: int, n_branches: int = 4):
+        self.problems = list(problems)
+        self.P = []
+        self.chains = []
+        for prob, P in zip(self.problems, P_list):
+            P = torch.as_tensor(P)
+            if P.dim() == 1:
+                P = P[None]
+            P = P.to(prob.device).to(torch.complex128).contiguous()
+            r, dev = P.shape[0], prob.device
+            self.P.append(P)
+            self.chains.append(dict(a=torch.empty(r, n_steps, dtype=torch.float64, device=dev),
+                                    b=torch.empty(r, n_steps + 1, dtype=torch.float64, device=dev),
+                                    pnorm2=torch.empty(r, dtype=torch.float64, device=dev),
+                                    steps=torch.empty(r, dtype=torch.int32, device=dev),
+                                    status=torch.empty(r, dtype=torch.int32, device=dev)))
+        self.n_steps = n_steps
+        c = self.chains
+        self.batch = bse_batch_create([p.plan for p in self.problems], self.P, [P.shape[0] for P in self.P],
+                                      n_steps, [x["a"] for x in c], [x["b"] for x in c], [x["pnorm2"] for x in c],
+                                      [x["steps"] for x in c], [x["status"] for x in c], n_branches)
+
+    def run(self, stream=None):
+        bse_batch_launch(self.batch, stream)
+        return self.chains
+
+    def close(self):
+        if getattr(self, "batch", None) is not None:
+            torch.cuda.synchronize(self.problems[0].device)   # no launch may still run
+            bse_batch_destroy(self.batch)
+            self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- one Hamiltonian on the device ------------------------------------------------------

@@ -29,6 +29,8 @@ static bse_status hip_fail(hipError_t e, const char* what) {
     return BSE_ERR_HIP;
 }
 
+bse_status hip_fail_status(hipError_t e, const char* what) { return hip_fail(e, what); }
+
 bool make_geometry(const bse_dims* d, Geometry* g) {
     if (!d) {
         set_error("dims is NULL");
@@ -184,6 +186,27 @@ hipError_t launch_continued_fraction(const double* a, const double* b, int lda, 
     hipLaunchKernelGGL(k_continued_fraction, dim3(nb), dim3(kBlock), 0, s, a, b, lda, ldb, pnorm2, steps, n_chains,
                        prefactor, omega, n_omega, eta, eps_re, eps_im);
     return hipGetLastError();
+}
+
+hipError_t enqueue_haydock(Plan& p, const double* P, int n_rhs, int n_steps, double* a, double* b, double* pnorm2,
+                           int32_t* steps_done, int32_t* status, hipStream_t stream) {
+    const int lda = n_steps, ldb = n_steps + 1;
+    void* A = p.ws + p.L.vec_a;  // u_{i-1}, then w, then u_{i+1}
+    void* B = p.ws + p.L.vec_b;  // u_i
+    // u_1 = P, ||u_1||, ||P||, coarse vector of psi_1; zero-fills a and b
+    hipError_t e = launch_restrict(p, RESTRICT_INIT, nullptr, nullptr, nullptr, P, B, 0, a, b, lda, ldb, n_rhs,
+                                   stream);
+    if (e == hipSuccess) e = launch_collapse(p, COLLAPSE_INIT, 0, b, ldb, n_rhs, stream);
+    for (int i = 0; i < n_steps && e == hipSuccess; ++i) {
+        e = launch_gemv(p, n_rhs, stream);
+        if (e == hipSuccess) e = launch_prolong(p, PROLONG_LANCZOS, B, A, i, n_rhs, stream);
+        if (e == hipSuccess)
+            e = launch_restrict(p, RESTRICT_UPDATE, nullptr, A, B, nullptr, A, i, a, b, lda, ldb, n_rhs, stream);
+        if (e == hipSuccess) e = launch_collapse(p, COLLAPSE_STEP, i, b, ldb, n_rhs, stream);
+        std::swap(A, B);
+    }
+    if (e == hipSuccess) e = launch_chain_report(p, n_steps, pnorm2, steps_done, status, n_rhs, stream);
+    return e;
 }
 
 }  // namespace bse
@@ -366,22 +389,7 @@ bse_status bse_haydock_run(bse_plan* plan, const double* P, int32_t n_rhs, int32
         set_error("bse_haydock_run: n_rhs must be in [1, %d] and n_steps >= 1", p.g.max_rhs);
         return BSE_ERR_INVALID_ARG;
     }
-    const int lda = n_steps, ldb = n_steps + 1;
-    void* A = p.ws + p.L.vec_a;  // u_{i-1}, then w, then u_{i+1}
-    void* B = p.ws + p.L.vec_b;  // u_i
-    // u_1 = P, ||u_1||, ||P||, coarse vector of psi_1; zero-fills a and b
-    hipError_t e = launch_restrict(p, RESTRICT_INIT, nullptr, nullptr, nullptr, P, B, 0, a, b, lda, ldb, n_rhs,
-                                   stream);
-    if (e == hipSuccess) e = launch_collapse(p, COLLAPSE_INIT, 0, b, ldb, n_rhs, stream);
-    for (int i = 0; i < n_steps && e == hipSuccess; ++i) {
-        e = launch_gemv(p, n_rhs, stream);
-        if (e == hipSuccess) e = launch_prolong(p, PROLONG_LANCZOS, B, A, i, n_rhs, stream);
-        if (e == hipSuccess)
-            e = launch_restrict(p, RESTRICT_UPDATE, nullptr, A, B, nullptr, A, i, a, b, lda, ldb, n_rhs, stream);
-        if (e == hipSuccess) e = launch_collapse(p, COLLAPSE_STEP, i, b, ldb, n_rhs, stream);
-        std::swap(A, B);
-    }
-    if (e == hipSuccess) e = launch_chain_report(p, n_steps, pnorm2, steps_done, status, n_rhs, stream);
+    hipError_t e = enqueue_haydock(p, P, n_rhs, n_steps, a, b, pnorm2, steps_done, status, stream);
     return e == hipSuccess ? BSE_OK : hip_fail(e, "bse_haydock_run");
 }
 

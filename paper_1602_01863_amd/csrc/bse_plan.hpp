@@ -165,6 +165,10 @@ enum { COLLAPSE_PLAIN = 0, COLLAPSE_INIT = 1, COLLAPSE_STEP = 2 };
 enum { PROLONG_PLAIN = 0, PROLONG_LANCZOS = 1 };
 
 void set_error(const char* fmt, ...);
+// every launch of one Haydock run (Eqs. ai-ci) on `stream`, as bse_haydock_run
+hipError_t enqueue_haydock(Plan& p, const double* P, int n_rhs, int n_steps, double* a, double* b, double* pnorm2,
+                           int32_t* steps_done, int32_t* status, hipStream_t stream);
+bse_status hip_fail_status(hipError_t e, const char* what);
 // bytes of shared memory (static + dynamic) one block may use on the current device
 size_t lds_limit();
 

@@ -9,7 +9,7 @@ or continued fraction).  Both the CPU oracle and the HIP path consume what it
 produces.
 """
 
-from .configs import CONFIGS, BSEConfig, get_config, tiny_config
+from .configs import CONFIGS, BSEConfig, batch_configs, get_config, tiny_config
 from .model import (
     TBModel,
     BandStructure,
@@ -24,6 +24,7 @@ __all__ = [
     "CONFIGS",
     "BSEConfig",
     "get_config",
+    "batch_configs",
     "tiny_config",
     "TBModel",
     "BandStructure",

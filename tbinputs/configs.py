@@ -37,6 +37,8 @@ class BSEConfig:
     g2_max: int = 4               # |G|^2 cut of the plane-wave sums (33 G)
     kernel_energy: float = 6.0    # eV, kernel energy scale (divided by dense N_k)
     q0_quad: int = 16             # midpoint points per axis for the q->0 average
+    # finite-difference displaced structure: (delta, direction seed) added to every H_R
+    perturb: tuple | None = None
     extra: dict = field(default_factory=dict, compare=False, hash=False)
 
     # ---- derived sizes -------------------------------------------------------
@@ -100,6 +102,31 @@ CONFIGS = {
 
 def get_config(name: str) -> BSEConfig:
     return CONFIGS[name.lower()]
+
+
+# batching workload: 3 grids x 8 seeded displacement directions x (+delta, -delta)
+BATCH_GRIDS = ((4, 2), (6, 3), (8, 4))
+BATCH_DIRECTIONS = 8
+BATCH_DELTA = 0.01
+
+
+def batch_configs() -> list:
+    """The 48 uneven Hamiltonians of the batching workload.
+
+    One seeded 9-orbital crystal (seed 3) displaced by +-delta (delta = 0.01) along
+    8 seeded directions, each structure on 3 grids (4^3 x 2, 6^3 x 3, 8^3 x 4);
+    nv = 3, nc = 3 for +delta and 6 for -delta; 3 polarisations, 200 steps, FP32.
+    """
+    out = []
+    for n_coarse, n_div in BATCH_GRIDS:
+        for d in range(BATCH_DIRECTIONS):
+            for sign in (1, -1):
+                nc = 3 if sign > 0 else 6
+                out.append(BSEConfig(name=f"c3_{n_coarse}x{n_div}_d{d}{'p' if sign > 0 else 'm'}", n_orb=9, nv=3,
+                                     nc=nc, n_coarse=n_coarse, n_div=n_div, seed=3, steps=200, n_pol=3,
+                                     omega_max=15.0, n_omega=3000, eta=0.05, dtype="c64",
+                                     perturb=(sign * BATCH_DELTA, 1000 + d)))
+    return out
 
 
 def tiny_config(n_coarse=2, n_div=2, nv=2, nc=2, n_orb=None, seed=7, dtype="c128",

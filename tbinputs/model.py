@@ -88,6 +88,8 @@ def make_model(cfg: BSEConfig, seed: int | None = None, perturb: tuple | None = 
     displaced structure.
     """
     seed = cfg.seed if seed is None else seed
+    if perturb is None:
+        perturb = cfg.perturb
     rng = np.random.default_rng(seed)
     n = cfg.n_orb
     R = LATTICE_R
