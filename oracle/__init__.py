@@ -21,7 +21,11 @@ spectra"):
                 kernel; Eqs. (matmul1)-(matmul3) on-the-fly product, both with
                 the corner sum collapsed first and literally.
 * ``lanczos``   Eqs. (ai)-(ci) Haydock-Lanczos chain, Eq. (fraccont)
-                continued fraction, Eq. (epsmacro) by diagonalisation.
+                continued fraction (also closed by a constant-coefficient
+                tail), Eq. (epsmacro) by diagonalisation.
+* ``mlp``       the learned terminator's network (dense layers, GELU, mean
+                squared error, Adam): textbook definitions, no part of the
+                paper.
 
 Every function here is pinned by a CPU test against something other than
 itself (closed forms, invariants, brute force, textbook routines).
@@ -44,11 +48,20 @@ from .kernel import (
     coarse_kernel_block_rows,
 )
 from .matvec import InterpOperator, transition_energies
-from .lanczos import haydock, continued_fraction, eigh_spectrum, ip_spectrum
+from .lanczos import (
+    haydock,
+    continued_fraction,
+    continued_fraction_terminated,
+    constant_chain_g,
+    eigh_spectrum,
+    ip_spectrum,
+)
+from . import mlp
 
 __all__ = [
     "corner_offsets", "neighbour_table", "trilinear_weights", "nearest_corner_weights",
     "dense_index_map", "fold_int", "overlaps", "g_vectors", "w_model", "w_q0_average",
     "coarse_kernel", "coarse_kernel_block_rows", "InterpOperator", "transition_energies",
-    "haydock", "continued_fraction", "eigh_spectrum", "ip_spectrum",
+    "haydock", "continued_fraction", "continued_fraction_terminated", "constant_chain_g",
+    "eigh_spectrum", "ip_spectrum", "mlp",
 ]

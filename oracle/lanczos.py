@@ -102,6 +102,48 @@ def continued_fraction(a: np.ndarray, b: np.ndarray, pnorm2, prefactor: float,
     return out
 
 
+def constant_chain_g(z, a_inf: float, b_inf: float):
+    """Resolvent of a semi-infinite chain with constant coefficients a_inf, b_inf:
+    g = 1 / (z - a_inf - b_inf^2 g), the root that vanishes as |z| grows, i.e. the
+    one with Im g < 0 for Im z > 0 (semicircle of half-width 2 b_inf).
+
+    This is the usual closure of a Lanczos continued fraction once the
+    coefficients have settled; the paper leaves the tail of Eq. (fraccont) open.
+    """
+    z = np.asarray(z, dtype=np.complex128)
+    x = z - a_inf
+    if b_inf == 0:
+        return 1.0 / x
+    root = np.sqrt(x * x - 4.0 * b_inf * b_inf)
+    g1 = (x - root) / (2.0 * b_inf * b_inf)
+    g2 = (x + root) / (2.0 * b_inf * b_inf)
+    return np.where(g1.imag <= 0, g1, g2)
+
+
+def continued_fraction_terminated(a: np.ndarray, b: np.ndarray, pnorm2, prefactor: float,
+                                  omega: np.ndarray, eta: float, a_inf, b_inf) -> np.ndarray:
+    """eps_M(omega) from m coefficients a_1..a_m, b_1..b_{m+1} closed by the constant
+    chain (a_inf, b_inf) beyond a_m: t_m = z - a_m - b_{m+1}^2 g_inf(z), then
+    t_i = z - a_i - b_{i+1}^2 / t_{i+1} and eps_M = 1 - C ||P||^2 / t_1."""
+    a = np.atleast_2d(a)
+    b = np.atleast_2d(b)
+    pnorm2 = np.atleast_1d(pnorm2)
+    a_inf = np.atleast_1d(a_inf)
+    b_inf = np.atleast_1d(b_inf)
+    n_rhs, m = a.shape
+    z = np.asarray(omega, dtype=np.float64) + 1j * eta
+    out = np.empty((n_rhs, z.shape[0]), dtype=np.complex128)
+    for r in range(n_rhs):
+        if pnorm2[r] == 0:
+            out[r] = 1.0
+            continue
+        t = z - a[r, m - 1] - b[r, m] ** 2 * constant_chain_g(z, a_inf[r], b_inf[r])
+        for i in range(m - 2, -1, -1):
+            t = z - a[r, i] - b[r, i + 1] ** 2 / t
+        out[r] = 1.0 - prefactor * pnorm2[r] / t
+    return out
+
+
 def eigh_spectrum(H: np.ndarray, P: np.ndarray, prefactor: float, omega: np.ndarray,
                   eta: float) -> np.ndarray:
     """eps_M(omega) from the eigenpairs of a Hermitian H, Eq. (epsmacro)."""
