@@ -256,6 +256,61 @@ bse_status bse_batch_create(bse_plan* const* plans, int32_t n_plans, const doubl
 bse_status bse_batch_launch(bse_batch* batch, hipStream_t stream);
 void bse_batch_destroy(bse_batch* batch);
 
+/* ---- Learned continued-fraction terminator -------------------------------------
+ * The paper leaves the tail of Eq. (fraccont) open (the chain is run until the
+ * spectrum has converged).  These calls serve a small dense network that predicts
+ * the coefficients after the first m from the first m, and the continued fraction
+ * closed by a constant tail.  All arrays are device pointers, row-major.
+ *
+ * Dense layer y = act(x W^T + b): x [batch][n_in], W [n_out][n_in], b [n_out],
+ * z and y [batch][n_out] (FP32).  act: BSE_ACT_NONE, or BSE_ACT_GELU (the exact
+ * z Phi(z) form).  z receives the pre-activation (may be NULL when y is given and
+ * no backward pass follows); y may be NULL when z is given.
+ */
+typedef enum { BSE_ACT_NONE = 0, BSE_ACT_GELU = 1 } bse_act;
+bse_status bse_dense_forward(const float* x, const float* W, const float* b, float* z, float* y,
+                             int32_t batch, int32_t n_in, int32_t n_out, int32_t act,
+                             hipStream_t stream);
+
+/* Backward pass of the same layer for a scalar loss L with dL/dy = dy:
+ * dW = dz^T x, db = column sums of dz, dx = dz W (skipped when dx is NULL), with
+ * dz = dy * act'(z) written to work [batch][n_out] (caller-owned scratch). */
+bse_status bse_dense_backward(const float* x, const float* W, const float* z, const float* dy,
+                              float* dx, float* dW, float* db, int32_t batch, int32_t n_in,
+                              int32_t n_out, int32_t act, float* work, hipStream_t stream);
+
+/* Mean squared error over n entries: *loss = mean (y - t)^2 (FP64, fixed-order
+ * sum, one device double) and dy = 2 (y - t) / n (skipped when dy is NULL). */
+bse_status bse_mse_loss(const float* y, const float* t, float* dy, double* loss, int64_t n,
+                        hipStream_t stream);
+
+/* One Adam update (Kingma and Ba, Alg. 1) of n parameters p with gradient g and
+ * moments m, v (updated in place); t >= 1 is the step count for the bias correction. */
+bse_status bse_adam_step(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                         float beta1, float beta2, float eps, int32_t t, hipStream_t stream);
+
+/* FP32 -> BF16 (round to nearest even), n entries; y holds the 16-bit patterns. */
+bse_status bse_to_bf16(const float* x, uint16_t* y, int64_t n, hipStream_t stream);
+
+/* Inference layer on the matrix cores: x [batch][n_in] and W [n_out][n_in] in BF16
+ * (16-byte aligned, n_in a multiple of 32), FP32 accumulation, y = act(x W^T + b)
+ * written as BF16 (y_bf16, the next layer's input) and/or FP32 (y_f32). */
+bse_status bse_dense_forward_bf16(const uint16_t* x, const uint16_t* W, const float* b,
+                                  uint16_t* y_bf16, float* y_f32, int32_t batch, int32_t n_in,
+                                  int32_t n_out, int32_t act, hipStream_t stream);
+
+/* eps_M (Eq. fraccont) from the first m coefficients a_1..a_m, b_1..b_{m+1} of each
+ * chain (rows of a [n_chains][lda], b [n_chains][ldb]) closed by the constant chain
+ * (a_inf, b_inf) of that chain: t_m = z - a_m - b_{m+1}^2 g(z) with g the root of
+ * b_inf^2 g^2 - (z - a_inf) g + 1 = 0 that has Im g <= 0, then t_i = z - a_i -
+ * b_{i+1}^2 / t_{i+1} and eps_M = 1 - prefactor ||P||^2 / t_1.  eta > 0. */
+bse_status bse_continued_fraction_terminated(const double* a, const double* b, int32_t lda,
+                                             int32_t ldb, int32_t m, const double* pnorm2,
+                                             const double* a_inf, const double* b_inf,
+                                             int32_t n_chains, double prefactor, const double* omega,
+                                             int32_t n_omega, double eta, double* eps_re,
+                                             double* eps_im, hipStream_t stream);
+
 /* Tunables of the coarse product: column splits (0 = automatic).  For sweeps. */
 bse_status bse_plan_set_gemv_splits(bse_plan* plan, int32_t n_split);
 

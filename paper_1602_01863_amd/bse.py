@@ -40,8 +40,10 @@ EXPORTED = [
     "bse_build_coarse_kernel", "bse_plan_create", "bse_plan_destroy", "bse_interp_matvec",
     "bse_haydock_run", "bse_continued_fraction", "bse_plan_set_timing", "bse_plan_get_timing",
     "bse_plan_set_gemv_splits", "bse_plan_set_restrict_group", "bse_batch_create", "bse_batch_launch",
-    "bse_batch_destroy",
+    "bse_batch_destroy", "bse_dense_forward", "bse_dense_backward", "bse_mse_loss", "bse_adam_step",
+    "bse_to_bf16", "bse_dense_forward_bf16", "bse_continued_fraction_terminated",
 ]
+BSE_ACT_NONE, BSE_ACT_GELU = 0, 1
 
 
 class BSEError(RuntimeError):
@@ -87,6 +89,15 @@ def _load():
         "bse_batch_create": (i32, [P(vp), i32, P(vp), P(i32), i32, P(vp), P(vp), P(vp), P(vp), P(vp), i32, P(vp)]),
         "bse_batch_launch": (i32, [vp, vp]),
         "bse_batch_destroy": (None, [vp]),
+        "bse_dense_forward": (i32, [vp, vp, vp, vp, vp, i32, i32, i32, i32, vp]),
+        "bse_dense_backward": (i32, [vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, vp, vp]),
+        "bse_mse_loss": (i32, [vp, vp, vp, vp, i64, vp]),
+        "bse_adam_step": (i32, [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, i32, vp]),
+        "bse_to_bf16": (i32, [vp, vp, i64, vp]),
+        "bse_dense_forward_bf16": (i32, [vp, vp, vp, vp, vp, i32, i32, i32, i32, vp]),
+        "bse_continued_fraction_terminated": (i32, [vp, vp, i32, i32, i32, vp, vp, vp, i32, dbl, vp, i32, dbl,
+                                                    vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -271,6 +282,45 @@ class BSEBatch:
             self.close()
         except Exception:
             pass
+
+
+# ---- learned terminator: network and closed continued fraction -------------------------
+def bse_dense_forward(x, W, b, z, y, batch, n_in, n_out, act, stream=None):
+    _check(_lib.bse_dense_forward(_ptr(x), _ptr(W), _ptr(b), _ptr(z), _ptr(y), int(batch), int(n_in), int(n_out),
+                                  int(act), _stream(stream)), "bse_dense_forward")
+
+
+def bse_dense_backward(x, W, z, dy, dx, dW, db, batch, n_in, n_out, act, work, stream=None):
+    _check(_lib.bse_dense_backward(_ptr(x), _ptr(W), _ptr(z), _ptr(dy), _ptr(dx), _ptr(dW), _ptr(db), int(batch),
+                                   int(n_in), int(n_out), int(act), _ptr(work), _stream(stream)),
+           "bse_dense_backward")
+
+
+def bse_mse_loss(y, t, dy, loss, n, stream=None):
+    _check(_lib.bse_mse_loss(_ptr(y), _ptr(t), _ptr(dy), _ptr(loss), int(n), _stream(stream)), "bse_mse_loss")
+
+
+def bse_adam_step(p, g, m, v, n, lr, beta1, beta2, eps, t, stream=None):
+    _check(_lib.bse_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), int(n), float(lr), float(beta1), float(beta2),
+                              float(eps), int(t), _stream(stream)), "bse_adam_step")
+
+
+def bse_to_bf16(x, y, n, stream=None):
+    _check(_lib.bse_to_bf16(_ptr(x), _ptr(y), int(n), _stream(stream)), "bse_to_bf16")
+
+
+def bse_dense_forward_bf16(x, W, b, y_bf16, y_f32, batch, n_in, n_out, act, stream=None):
+    _check(_lib.bse_dense_forward_bf16(_ptr(x), _ptr(W), _ptr(b), _ptr(y_bf16), _ptr(y_f32), int(batch), int(n_in),
+                                       int(n_out), int(act), _stream(stream)), "bse_dense_forward_bf16")
+
+
+def bse_continued_fraction_terminated(a, b, lda, ldb, m, pnorm2, a_inf, b_inf, n_chains, prefactor, omega, n_omega,
+                                      eta, eps_re, eps_im, stream=None):
+    _check(_lib.bse_continued_fraction_terminated(_ptr(a), _ptr(b), int(lda), int(ldb), int(m), _ptr(pnorm2),
+                                                  _ptr(a_inf), _ptr(b_inf), int(n_chains), float(prefactor),
+                                                  _ptr(omega), int(n_omega), float(eta), _ptr(eps_re),
+                                                  _ptr(eps_im), _stream(stream)),
+           "bse_continued_fraction_terminated")
 
 
 # ---- one Hamiltonian on the device ------------------------------------------------------
