@@ -14,8 +14,15 @@ def test_normalise_targets_denormalise_round_trip():
     assert x.shape == (n, T.N_IN)
     assert np.allclose(x[:, :T.M_IN].mean(axis=1), 0.0, atol=1e-12)
     assert np.allclose(x[:, T.M_IN:].mean(axis=1), 0.5)          # b / (2 mean b)
-    y = T.targets(a, b, c, s)
+    y = T.targets(a, b, c, s, smooth=1)
     assert y.shape == (n, T.N_OUT)
+    # the training targets are the same residuals, moving-averaged along the tail
+    ys = T.targets(a, b, c, s)
+    assert np.allclose(ys[:, :T.M_OUT], T.moving_average(y[:, :T.M_OUT], T.SMOOTH))
+    assert np.allclose(ys[:, T.M_OUT:2 * T.M_OUT], T.moving_average(y[:, T.M_OUT:2 * T.M_OUT], T.SMOOTH))
+    assert np.array_equal(ys[:, 2 * T.M_OUT:], y[:, 2 * T.M_OUT:])
+    const = np.full((2, 40), 3.0)
+    assert np.allclose(T.moving_average(const, 8), 3.0)
     at, bt, ainf, binf = T.denormalise(y, a, b, s)
     assert np.allclose(at, a[:, T.M_IN:T.M_IN + T.M_OUT], rtol=1e-13)
     assert np.allclose(bt, b[:, T.M_IN + 1:T.M_IN + T.M_OUT + 1], rtol=1e-13)
