@@ -66,8 +66,8 @@ def _args():
 def main():
     args = _args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
-              "the multi-GPU layout is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: the Haydock path runs on one GPU (--gpus {args.gpus} requested); "
+              "sharding the coarse cells over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -6,7 +6,7 @@ dense network (4 layers, width 128, GELU) predicts, from the first M_IN = 64
 coefficients of a chain, the next M_OUT = 192 coefficients and the asymptotic pair
 (a_inf, b_inf) that closes the fraction as a constant chain.  The chain can then
 stop after 64 steps; when an error estimate says the closed spectrum is not good
-enough, the full plain chain is run instead (the fallback, which is also the judge
+enough, the full plain chain is run instead (the fallback, which is also the reference
 in the tests).
 
 Everything runs in the library's kernels: training (FP32 dense layers, GELU, mean
