@@ -23,6 +23,9 @@ spectra"):
 * ``lanczos``   Eqs. (ai)-(ci) Haydock-Lanczos chain, Eq. (fraccont)
                 continued fraction (also closed by a constant-coefficient
                 tail), Eq. (epsmacro) by diagonalisation.
+* ``m3``        Sec. 4, Method 3: the divergent part of Eq. (diverg)
+                interpolated and combined with the dense-mesh q inside a band
+                ||k - k'|| <= w d, as a sparse correction of the Method 1 product.
 * ``mlp``       the learned terminator's network (dense layers, GELU, mean
                 squared error, Adam): textbook definitions, no part of the
                 paper.
@@ -46,6 +49,11 @@ from .kernel import (
     w_q0_average,
     coarse_kernel,
     coarse_kernel_block_rows,
+    screening_kappa2,
+    s_shape,
+    s_q0_average,
+    coarse_shape,
+    divergence_coefficient,
 )
 from .matvec import InterpOperator, transition_energies
 from .lanczos import (
@@ -56,12 +64,13 @@ from .lanczos import (
     eigh_spectrum,
     ip_spectrum,
 )
-from . import mlp
+from . import m3, mlp
 
 __all__ = [
     "corner_offsets", "neighbour_table", "trilinear_weights", "nearest_corner_weights",
     "dense_index_map", "fold_int", "overlaps", "g_vectors", "w_model", "w_q0_average",
     "coarse_kernel", "coarse_kernel_block_rows", "InterpOperator", "transition_energies",
     "haydock", "continued_fraction", "continued_fraction_terminated", "constant_chain_g",
-    "eigh_spectrum", "ip_spectrum", "mlp",
+    "eigh_spectrum", "ip_spectrum", "mlp", "m3", "screening_kappa2", "s_shape", "s_q0_average",
+    "coarse_shape", "divergence_coefficient",
 ]

@@ -29,6 +29,18 @@ Readings taken where the paper is silent:
   transpose, and diagonal blocks are replaced by (A + A^H) / 2.
 
 Transition index on the coarse mesh: T = (k~ * nv + n1) * nc + n2.
+
+Divergent part (Eq. diverg, used by Method 3 of Sec. 4).  The paper splits
+each kernel element into a/q^2 + b/q + c.  For this model the only term that
+varies sharply as q -> 0 is the G = 0 direct term, and since
+W(q) = s(q) / (pi eps_inf) with s(q) = 1 / (|q|^2 + kappa^2) and
+kappa^2 = lambda^2 / (4 pi^2 eps_inf) (q reduced), the split reads
+    K_c = a_c s(q) + c_c,   b = 0,
+    a_c = -(kernel_energy / N_k(dense)) / (pi eps_inf) M_cc'(k,k';q) conj(M_vv'(k,k';q)),
+with s(q) in place of 1/q^2 (the two agree as lambda -> 0: the model's
+Coulomb tail is screened).  Where K_c uses the mini-cell mean of W at q = 0,
+the split uses the mini-cell mean of s.  b = 0 because W is diagonal in G
+(no head-wing terms).
 """
 
 from __future__ import annotations
@@ -124,21 +136,81 @@ def coarse_kernel(vecs_coarse: np.ndarray, tau: np.ndarray, nv: int, nc: int, n_
 
     cfg_like supplies eps_inf, lam, g2_max, kernel_energy and q0_quad.
     """
-    nk = n_c ** 3
-    npair = nv * nc
     prm = _params(cfg_like)
+    return _assemble_hermitian(
+        lambda ks, kps: _direct_formula_blocks(vecs_coarse, tau, nv, nc, n_c, n_div, ks, kps, **prm),
+        n_c ** 3, nv * nc, chunk)
+
+
+def _assemble_hermitian(blocks, nk: int, npair: int, chunk: int) -> np.ndarray:
+    """[nk npair, nk npair] matrix from blocks(ks, kps) evaluated for k <= k': the block
+    (k', k) is the conjugate transpose of (k, k'), diagonal blocks are (A + A^H) / 2."""
     iu, ju = np.triu_indices(nk)
     K = np.zeros((nk, npair, nk, npair), dtype=np.complex128)
     for s in range(0, iu.shape[0], chunk):
         ks, kps = iu[s:s + chunk], ju[s:s + chunk]
-        blk = _direct_formula_blocks(vecs_coarse, tau, nv, nc, n_c, n_div, ks, kps, **prm)
-        blk = blk.reshape(-1, npair, npair)
+        blk = blocks(ks, kps).reshape(-1, npair, npair)
         diag = ks == kps
         blk[diag] = 0.5 * (blk[diag] + blk[diag].conj().transpose(0, 2, 1))
         K[ks, :, kps, :] = blk
         off = ~diag
         K[kps[off], :, ks[off], :] = blk[off].conj().transpose(0, 2, 1)
     return K.reshape(nk * npair, nk * npair)
+
+
+# ---- Eq. (diverg): the divergent part of the kernel ----------------------------------
+def screening_kappa2(eps_inf: float, lam: float) -> float:
+    """kappa^2 of s(q) = 1 / (|q|^2 + kappa^2), W(q) = s(q) / (pi eps_inf), q reduced."""
+    return lam * lam / (4.0 * np.pi * np.pi * eps_inf)
+
+
+def s_shape(q: np.ndarray, kappa2: float) -> np.ndarray:
+    """s(q) = 1 / (|q|^2 + kappa^2) for reduced q[..., 3]."""
+    q = np.asarray(q, dtype=np.float64)
+    return 1.0 / (np.sum(q * q, axis=-1) + kappa2)
+
+
+def s_q0_average(n_c: int, n_div: int, kappa2: float, n_quad: int = 16) -> float:
+    """Mean of s(q) over the dense mini-cell q in [-1/2, 1/2)^3 / (n_c n_div), midpoint rule."""
+    t = ((np.arange(n_quad) + 0.5) / n_quad - 0.5) / (n_c * n_div)
+    q = np.stack(np.meshgrid(t, t, t, indexing="ij"), axis=-1).reshape(-1, 3)
+    return float(np.mean(s_shape(q, kappa2)))
+
+
+def coarse_shape(n_c: int, kappa2: float, s0: float) -> np.ndarray:
+    """S_c[k~, k~'] = s(q) with q = k~ - k~' folded (reduced), and s0 at q = 0."""
+    ijk = cell_coords(n_c)
+    q = fold_int(ijk[:, None, :] - ijk[None, :, :], n_c).astype(np.float64) / n_c
+    S = s_shape(q, kappa2)
+    np.fill_diagonal(S, s0)
+    return S
+
+
+def _divergence_blocks(vecs_coarse, tau, nv, nc, n_c, n_div, ks, kps, *, eps_inf, kernel_energy):
+    """Unsymmetrised blocks a[p, v, c, v', c'] of the coefficient of s(q) for pairs (ks[p], kps[p])."""
+    ks = np.asarray(ks)
+    kps = np.asarray(kps)
+    nkd = n_c ** 3 * n_div ** 3
+    ijk = cell_coords(n_c)
+    q = fold_int(ijk[ks] - ijk[kps], n_c).astype(np.float64) / n_c
+    A = vecs_coarse[ks]
+    B = vecs_coarse[kps]
+    ph = np.exp(2j * np.pi * (q @ tau.T))
+    mcc = _pair_density(A[:, nv:nv + nc], B[:, nv:nv + nc], ph)      # M_cc'(k,k';q)
+    mvv = _pair_density(A[:, :nv], B[:, :nv], ph)                    # M_vv'(k,k';q)
+    coef = -(kernel_energy / nkd) / (np.pi * eps_inf)
+    return coef * (mcc[:, None, :, None, :] * mvv.conj()[:, :, None, :, None])
+
+
+def divergence_coefficient(vecs_coarse: np.ndarray, tau: np.ndarray, nv: int, nc: int, n_c: int,
+                           n_div: int, cfg_like, chunk: int = 4096) -> np.ndarray:
+    """a_c [N_coarse, N_coarse] of Eq. (diverg) for the model kernel (see the module
+    notes): the G = 0 direct term of K_c equals a_c s(q); Hermitian by the same
+    construction as K_c."""
+    prm = dict(eps_inf=cfg_like.eps_inf, kernel_energy=cfg_like.kernel_energy)
+    return _assemble_hermitian(
+        lambda ks, kps: _divergence_blocks(vecs_coarse, tau, nv, nc, n_c, n_div, ks, kps, **prm),
+        n_c ** 3, nv * nc, chunk)
 
 
 def coarse_kernel_block_rows(vecs_coarse: np.ndarray, tau: np.ndarray, nv: int, nc: int,
