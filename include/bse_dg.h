@@ -311,6 +311,50 @@ bse_status bse_continued_fraction_terminated(const double* a, const double* b, i
                                              int32_t n_omega, double eta, double* eps_re,
                                              double* eps_im, hipStream_t stream);
 
+/* ---- Method 3: the divergence treated in a band along the diagonal (Sec. 4) ------
+ * Dense pairs with ||k - k'|| <= w d (d = 1 / n_coarse, the smallest distance between
+ * coarse points; reduced coordinates of the cubic cell, minimum image) take the
+ * coefficients of Eq. (diverg) interpolated like K_c (Eq. interp1) and combined with
+ * the dense-mesh q; all other pairs keep Method 1.  For the model kernel of
+ * bse_build_coarse_kernel the divergent part is the G = 0 direct term:
+ * K_c = a_c s(q) + c_c with s(q) = 1 / (|q|^2 + kappa^2), kappa^2 = lambda^2 /
+ * (4 pi^2 eps_inf), q reduced (the screened form of a / q^2; b = 0 because W is
+ * diagonal in G), and s at q = 0 replaced by its mean over the dense mini-cell
+ * (midpoint rule, q0_quad points per axis), as W is in K_c.  Inside the band
+ *   K^{M3}(k, k') = interp(a_c)(k, k') s(k - k') + interp(K_c - a_c S_c)(k, k'),
+ * i.e. the Method 1 kernel plus a block Delta(k, k + o) per dense point k and band
+ * offset o (integer offsets of the dense mesh with |o|^2 <= (w n_div)^2). */
+
+/* a_c (same layout and precision as K_c of bse_build_coarse_kernel): the coarse
+ * coefficient of s(q), -kernel_energy / N_k(dense) / (pi eps_inf) M_cc'(k~,k~';q)
+ * conj(M_vv'(k~,k~';q)) with the Hermitian construction of K_c. */
+bse_status bse_build_divergence_coefficient(const bse_dims* dims, const double* vecs_coarse,
+                                            const double* tau, const bse_kernel_model* model,
+                                            void* a_out, hipStream_t stream);
+
+/* Number of band offsets for width w >= 0 and the bytes of the band buffer for dims
+ * (BSE_ERR_INVALID_ARG when floor(w n_div) > 16, when 2 floor(w n_div) reaches the
+ * dense mesh n_coarse n_div, or when nv nc > 32). */
+bse_status bse_m3_band_info(const bse_dims* dims, double w, int32_t* n_offsets, size_t* band_bytes);
+
+/* Builds the band: the blocks Delta(k, k + o) from the overlaps d (layout of
+ * bse_build_overlaps), a_c and the model's eps_inf, lambda and q0_quad, in the
+ * storage precision of dims->dtype (FP64 for BSE_F64, FP32 otherwise), FP64
+ * arithmetic.  band: device, 256-byte aligned, >= band_bytes of bse_m3_band_info;
+ * it holds the offset table, the blocks and the scratch of the band product (one
+ * FP64 complex vector per right-hand side), so one band serves one plan at a time.
+ * The kernels are enqueued on `stream`. */
+bse_status bse_build_m3_band(const bse_dims* dims, const void* d, const void* a_coef,
+                             const bse_kernel_model* model, double w, void* band,
+                             size_t band_bytes, hipStream_t stream);
+
+/* Attaches a band built for the plan's dims and this w (band = NULL detaches it).
+ * From then on bse_interp_matvec and bse_haydock_run (and batches recorded later)
+ * apply H^{M3} = diag(delta) + K^i + Delta: before the prolong, a kernel forms
+ * y_k = sum_o Delta(k, k + o) x_{k+o} in FP64, and the prolong adds it.  The band
+ * must stay valid while the plan uses it. */
+bse_status bse_plan_set_m3_band(bse_plan* plan, void* band, double w);
+
 /* Tunables of the coarse product: column splits (0 = automatic).  For sweeps. */
 bse_status bse_plan_set_gemv_splits(bse_plan* plan, int32_t n_split);
 

@@ -108,8 +108,11 @@ def explicit_kernel(op, a_c: np.ndarray, S_c: np.ndarray, w: float, kappa2: floa
 
 
 def band_blocks(op, a_c: np.ndarray, S_c: np.ndarray, offsets: np.ndarray, s_d: np.ndarray,
-                ks=None) -> np.ndarray:
-    """Delta(k, k + o) [len(ks), n_off, npair, npair] from its definition (module notes)."""
+                ks=None, absolute: bool = False) -> np.ndarray:
+    """Delta(k, k + o) [len(ks), n_off, npair, npair] from its definition (module notes).
+
+    absolute=True takes the modulus of the scalar weights as well (with op and a_c
+    given as moduli, the result bounds the sum of |terms| of each entry)."""
     nv, nc = op.nv, op.nc
     npair = nv * nc
     ks = np.arange(op.nk) if ks is None else np.asarray(ks)
@@ -127,6 +130,8 @@ def band_blocks(op, a_c: np.ndarray, S_c: np.ndarray, offsets: np.ndarray, s_d: 
             Lp = L(kp)
             cp = op.corner_k[kp]
             g = op.fk[k][:, None] * op.fk[kp][None, :] * (s_d[j] - S_c[ck[:, None], cp[None, :]])
+            if absolute:
+                g = np.abs(g)
             blk = np.zeros((npair, npair), dtype=np.complex128)
             for z in range(8):
                 for zp in range(8):

@@ -42,6 +42,7 @@ EXPORTED = [
     "bse_plan_set_gemv_splits", "bse_plan_set_restrict_group", "bse_batch_create", "bse_batch_launch",
     "bse_batch_destroy", "bse_dense_forward", "bse_dense_backward", "bse_mse_loss", "bse_adam_step",
     "bse_to_bf16", "bse_dense_forward_bf16", "bse_continued_fraction_terminated",
+    "bse_build_divergence_coefficient", "bse_m3_band_info", "bse_build_m3_band", "bse_plan_set_m3_band",
 ]
 BSE_ACT_NONE, BSE_ACT_GELU = 0, 1
 
@@ -98,6 +99,10 @@ def _load():
         "bse_dense_forward_bf16": (i32, [vp, vp, vp, vp, vp, i32, i32, i32, i32, vp]),
         "bse_continued_fraction_terminated": (i32, [vp, vp, i32, i32, i32, vp, vp, vp, i32, dbl, vp, i32, dbl,
                                                     vp, vp, vp]),
+        "bse_build_divergence_coefficient": (i32, [P(Dims), vp, vp, P(KernelModel), vp, vp]),
+        "bse_m3_band_info": (i32, [P(Dims), dbl, P(i32), P(sz)]),
+        "bse_build_m3_band": (i32, [P(Dims), vp, vp, P(KernelModel), dbl, vp, sz, vp]),
+        "bse_plan_set_m3_band": (i32, [vp, vp, dbl]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -324,6 +329,33 @@ def bse_continued_fraction_terminated(a, b, lda, ldb, m, pnorm2, a_inf, b_inf, n
 
 
 # ---- one Hamiltonian on the device ------------------------------------------------------
+# ---- Method 3 (Sec. 4): the divergence treated in a band along the diagonal -----------
+def bse_build_divergence_coefficient(dims, vecs_coarse, tau, model: KernelModel, a_out, stream=None):
+    _check(_lib.bse_build_divergence_coefficient(ctypes.byref(dims), _ptr(vecs_coarse), _ptr(tau),
+                                                 ctypes.byref(model), _ptr(a_out), _stream(stream)),
+           "bse_build_divergence_coefficient")
+
+
+def bse_m3_band_info(dims, w: float):
+    """(number of band offsets, bytes of the band buffer)."""
+    n = ctypes.c_int32(0)
+    nb = ctypes.c_size_t(0)
+    _check(_lib.bse_m3_band_info(ctypes.byref(dims), float(w), ctypes.byref(n), ctypes.byref(nb)),
+           "bse_m3_band_info")
+    return n.value, nb.value
+
+
+def bse_build_m3_band(dims, d, a_coef, model: KernelModel, w: float, band, stream=None):
+    _check(_lib.bse_build_m3_band(ctypes.byref(dims), _ptr(d), _ptr(a_coef), ctypes.byref(model), float(w),
+                                  _ptr(band), band.numel() * band.element_size(), _stream(stream)),
+           "bse_build_m3_band")
+
+
+def bse_plan_set_m3_band(plan, band, w: float):
+    _check(_lib.bse_plan_set_m3_band(plan, _ptr(band) if band is not None else None, float(w)),
+           "bse_plan_set_m3_band")
+
+
 def _storage(dtype_code: int):
     """(matrix complex dtype, vector complex dtype) for a bse_dtype."""
     if dtype_code == BSE_F64:
@@ -430,6 +462,21 @@ class BSEProblem:
         bse_continued_fraction(a, b, a.shape[1], b.shape[1], chain["pnorm2"], chain["steps"], n_chains,
                                prefactor, om, om.numel(), eta, er, ei)
         return torch.complex(er, ei)
+
+    def set_m3(self, w):
+        """Method 3 with band width w (in units of the coarse spacing); None: Method 1.
+        Builds a_c and the band on the device and attaches it to the plan."""
+        if w is None:
+            bse_plan_set_m3_band(self.plan, None, 0.0)
+            self.band = self.a_coef = None
+            return
+        n_off, nbytes = bse_m3_band_info(self.dims, w)
+        self.a_coef = torch.empty(self.Nc, self.Nc, dtype=self.mat_dtype, device=self.device)
+        bse_build_divergence_coefficient(self.dims, self.vecs_coarse, self.tau, self.model, self.a_coef)
+        self.band = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        bse_build_m3_band(self.dims, self.d, self.a_coef, self.model, w, self.band)
+        bse_plan_set_m3_band(self.plan, self.band, w)
+        self.m3_offsets = n_off
 
     def set_timing(self, enable: bool):
         bse_plan_set_timing(self.plan, enable)

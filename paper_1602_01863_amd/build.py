@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libbse_dg.so")
-SOURCES = ["api.hip", "setup.hip", "hotpath.hip", "gemv.hip", "restrict.hip", "prolong.hip", "batch.hip", "mlp.hip"]
+SOURCES = ["api.hip", "setup.hip", "hotpath.hip", "gemv.hip", "restrict.hip", "prolong.hip", "batch.hip", "mlp.hip", "m3.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -198,7 +198,8 @@ hipError_t enqueue_haydock(Plan& p, const double* P, int n_rhs, int n_steps, dou
                                    stream);
     if (e == hipSuccess) e = launch_collapse(p, COLLAPSE_INIT, 0, b, ldb, n_rhs, stream);
     for (int i = 0; i < n_steps && e == hipSuccess; ++i) {
-        e = launch_gemv(p, n_rhs, stream);
+        e = launch_m3_apply(p, B, n_rhs, stream);   // Method 3 band of u_i (no-op without a band)
+        if (e == hipSuccess) e = launch_gemv(p, n_rhs, stream);
         if (e == hipSuccess) e = launch_prolong(p, PROLONG_LANCZOS, B, A, i, n_rhs, stream);
         if (e == hipSuccess)
             e = launch_restrict(p, RESTRICT_UPDATE, nullptr, A, B, nullptr, A, i, a, b, lda, ldb, n_rhs, stream);
@@ -370,8 +371,10 @@ bse_status bse_interp_matvec(bse_plan* plan, const void* x, void* y, int32_t n_r
         set_error("bse_interp_matvec: x and y must not alias");
         return BSE_ERR_INVALID_ARG;
     }
-    hipError_t e = launch_restrict(p, RESTRICT_PLAIN, x, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr,
-                                   0, 0, n_rhs, stream);
+    hipError_t e = launch_m3_apply(p, x, n_rhs, stream);   // Method 3 band (no-op without a band)
+    if (e == hipSuccess)
+        e = launch_restrict(p, RESTRICT_PLAIN, x, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0, 0,
+                            n_rhs, stream);
     if (e == hipSuccess) e = launch_collapse(p, COLLAPSE_PLAIN, 0, nullptr, 0, n_rhs, stream);
     if (e == hipSuccess) e = launch_gemv(p, n_rhs, stream);
     if (e == hipSuccess) e = launch_prolong(p, PROLONG_PLAIN, x, y, 0, n_rhs, stream);

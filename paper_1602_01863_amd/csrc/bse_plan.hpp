@@ -111,6 +111,10 @@ struct Plan {
     int64_t timed_launches;
     hipEvent_t* ev;
     int ev_cap;
+    // Method 3 band (m3.hip); m3_band == nullptr: Method 1 only
+    const char* m3_band;  // caller's band buffer: offset table, then the blocks
+    double2* m3_yb;       // band product [rhs][N] (FP64), the tail of the band buffer
+    int m3_noff_pad;      // band offsets, padded to whole chunks
 };
 
 // launches implemented in hotpath.hip (return hipSuccess or the launch error)
@@ -125,6 +129,9 @@ hipError_t launch_chain_report(const Plan& p, int n_steps, double* pnorm2, int32
                                int n_rhs, hipStream_t s);
 bool supported_bands(int nv, int nc);
 
+// Method 3 band product y_band = Band x (m3.hip), before the prolong, which adds it
+hipError_t launch_m3_apply(const Plan& p, const void* x, int n_rhs, hipStream_t s);
+
 // restrict tiles from the overlaps (restrict.hip), enqueued at plan creation
 hipError_t launch_swizzle(const Plan& p, hipStream_t s);
 // block-scaled coarse kernel and cleared qbar fragments (gemv.hip), at plan creation
@@ -137,6 +144,8 @@ hipError_t launch_overlaps(const Geometry& g, const double* vc, const double* vd
 hipError_t launch_transition_energies(const Geometry& g, const double* eps, double* out, hipStream_t s);
 hipError_t launch_coarse_kernel(const Geometry& g, const double* vecs, const double* tau,
                                 const bse_kernel_model& m, void* K, hipStream_t s);
+hipError_t launch_divergence_coefficient(const Geometry& g, const double* vecs, const double* tau,
+                                         const bse_kernel_model& m, void* A, hipStream_t s);
 hipError_t launch_continued_fraction(const double* a, const double* b, int lda, int ldb, const double* pnorm2,
                                      const int32_t* steps, int n_chains, double prefactor, const double* omega,
                                      int n_omega, double eta, double* eps_re, double* eps_im, hipStream_t s);

@@ -27,7 +27,8 @@ __global__ __launch_bounds__(256) void k_prolong1(const M2* __restrict__ d, cons
                                                  const double2* __restrict__ rvec, const V2* __restrict__ x,
                                                  V2* __restrict__ out, double* __restrict__ ppart,
                                                  const ChainState* __restrict__ chain, int n_c, int n_div,
-                                                 int neighbours, int64_t N, int n_rhs) {
+                                                 int neighbours, int64_t N, int n_rhs,
+                                                 const double2* __restrict__ yb) {
     constexpr int NP = NV * NC;
     constexpr int NE = NV * NV + NC * NC;
     const int ndiv3 = n_div * n_div * n_div;
@@ -55,6 +56,11 @@ __global__ __launch_bounds__(256) void k_prolong1(const M2* __restrict__ d, cons
                 const cd pv = ld(out + t0 + p);
                 acc[p].re = fma(-c_prev, pv.re, acc[p].re);
                 acc[p].im = fma(-c_prev, pv.im, acc[p].im);
+            }
+            if (yb) {   // Method 3 band product of u_i (uniform)
+                const double2 y = yb[t0 + p];
+                acc[p].re = fma(s_cur, y.x, acc[p].re);
+                acc[p].im = fma(s_cur, y.y, acc[p].im);
             }
         }
         for (int z = 0; z < 8; ++z) {
@@ -134,7 +140,8 @@ __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, NV, NC>
                                                          const double2* __restrict__ rvec, const V2* __restrict__ x,
                                                          V2* __restrict__ out, double* __restrict__ ppart,
                                                          const ChainState* __restrict__ chain, int n_c, int n_div,
-                                                         int neighbours, int64_t N) {
+                                                         int neighbours, int64_t N,
+                                                         const double2* __restrict__ yb) {
     constexpr int NP = NV * NC;
     constexpr int NE = NV * NV + NC * NC;
     constexpr int NCH = (NC + 1) / 2;
@@ -270,6 +277,7 @@ __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, NV, NC>
         // step its buffer holds no vector, and the select below drops it)
         V2 xr[NV][NCH], pr[NV][NCH];
         double dr[NV][NCH];
+        double2 yr[NV][NCH];
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -279,6 +287,12 @@ __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, NV, NC>
                 dr[v][q] = delta[kd * NP + p];
                 if (MODE == PROLONG_LANCZOS) pr[v][q] = out[t0 + p];
             }
+        if (yb) {   // Method 3 band product of u_i (uniform branch)
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int q = 0; q < NCH; ++q) yr[v][q] = yb[t0 + v * NC + min(h * NCH + q, NC - 1)];
+        }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int v = 0; v < NV; ++v)
@@ -298,6 +312,10 @@ __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, NV, NC>
                     const double pim = c_prev != 0.0 ? pv.im : 0.0;
                     w.re = fma(-c_prev, pre, w.re);
                     w.im = fma(-c_prev, pim, w.im);
+                }
+                if (yb) {
+                    w.re = fma(s_cur, yr[v][q].x, w.re);
+                    w.im = fma(s_cur, yr[v][q].y, w.im);
                 }
                 st(out + t0 + p, w);
                 if (MODE == PROLONG_LANCZOS) {
@@ -336,13 +354,14 @@ static void prolong3_go(const Plan& p, int mode, const V2* xv, V2* ov, const Cha
     const double2* rvec = reinterpret_cast<const double2*>(p.ws + p.L.rvec);
     double* ppart = reinterpret_cast<double*>(p.ws + p.L.ppart);
     const M2* d = reinterpret_cast<const M2*>(p.d);
+    const double2* yb = p.m3_band ? p.m3_yb : nullptr;
     dim3 grid(g.ncells), block(prolong3_threads<NR>());
     if (mode == PROLONG_PLAIN)
         hipLaunchKernelGGL((k_prolong3<M2, V2, NV, NC, PROLONG_PLAIN, NR>), grid, block, lds, s, d, p.delta, rvec, xv,
-                           ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N);
+                           ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, yb);
     else
         hipLaunchKernelGGL((k_prolong3<M2, V2, NV, NC, PROLONG_LANCZOS, NR>), grid, block, lds, s, d, p.delta, rvec,
-                           xv, ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N);
+                           xv, ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, yb);
 }
 
 template <class M2, class V2, int NV, int NC>
@@ -368,12 +387,13 @@ hipError_t prolong_launch(const Plan& p, int mode, const void* x, void* out, int
         }
     } else {
         dim3 grid(g.ncells), block(kWave * n_rhs);
+        const double2* yb = p.m3_band ? p.m3_yb : nullptr;
         if (mode == PROLONG_PLAIN)
             hipLaunchKernelGGL((k_prolong1<M2, V2, NV, NC, PROLONG_PLAIN>), grid, block, 0, s, d, p.delta, rvec, xv,
-                               ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
+                               ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, n_rhs, yb);
         else
             hipLaunchKernelGGL((k_prolong1<M2, V2, NV, NC, PROLONG_LANCZOS>), grid, block, 0, s, d, p.delta, rvec,
-                               xv, ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, n_rhs);
+                               xv, ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, n_rhs, yb);
     }
     return hipGetLastError();
 }

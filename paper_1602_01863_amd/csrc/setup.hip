@@ -87,7 +87,11 @@ __device__ __forceinline__ int enumerate_g(int g2max, int* gx, int* gy, int* gz)
     return n;
 }
 
-template <class M2>
+// COEF = false: the coarse kernel K_c.  COEF = true: the coefficient a_c of the
+// divergent part of Eq. (diverg) for this model, i.e. the G = 0 direct term with W
+// replaced by 1 / (pi eps_inf) (W(q) = s(q) / (pi eps_inf), s = 1 / (|q|^2 + kappa^2)),
+// so that the G = 0 direct term of K_c is a_c s(q); no exchange.
+template <class M2, bool COEF>
 __global__ __launch_bounds__(256) void k_coarse_kernel(const double2* __restrict__ vecs, const double* __restrict__ tau,
                                                        M2* __restrict__ K, int n_c, int n_div, int nv, int nc, int n_orb,
                                                        double eps_inf, double lam, double scale, int g2max, int q0q) {
@@ -132,7 +136,7 @@ __global__ __launch_bounds__(256) void k_coarse_kernel(const double2* __restrict
 
     // W(q -> 0) averaged over the dense mini-cell, midpoint rule (diagonal blocks only)
     double wq0 = 0.0;
-    if (k == kp) {
+    if (!COEF && k == kp) {
         const int nq3 = q0q * q0q * q0q;
         const double h = 1.0 / ((double)n_c * n_div);
         double s = 0.0;
@@ -179,7 +183,7 @@ __global__ __launch_bounds__(256) void k_coarse_kernel(const double2* __restrict
         accd[j] = cmake(0.0, 0.0);
     }
     // exchange: X[(v c),(v' c')] = sum_{G != 0} v(G) M_cv(k;G) conj(M_c'v'(kp;G))
-    for (int j = 0; j < kMaxOut; ++j) {
+    for (int j = 0; j < kMaxOut && !COEF; ++j) {
         const int o = threadIdx.x + j * blockDim.x;
         if (o >= nout) break;
         const int pr = o / np, pc = o % np;
@@ -198,9 +202,11 @@ __global__ __launch_bounds__(256) void k_coarse_kernel(const double2* __restrict
     }
     // direct: D[(v c),(v' c')] = sum_G W(q+G) M_cc'(k,kp;q+G) conj(M_vv'(k,kp;q+G))
     for (int g = 0; g < ng; ++g) {
+        if (COEF && (gx[g] != 0 || gy[g] != 0 || gz[g] != 0)) continue;   // uniform
         const double Qx = q[0] + gx[g], Qy = q[1] + gy[g], Qz = q[2] + gz[g];
         double W = 4.0 * M_PI / (eps_inf * 4.0 * M_PI * M_PI * (Qx * Qx + Qy * Qy + Qz * Qz) + lam * lam);
         if (k == kp && gx[g] == 0 && gy[g] == 0 && gz[g] == 0) W = wq0;
+        if (COEF) W = 1.0 / (M_PI * eps_inf);
         if (threadIdx.x < n_orb) {
             double sn, cs;
             const int o = threadIdx.x;
@@ -288,20 +294,31 @@ hipError_t launch_transition_energies(const Geometry& g, const double* eps, doub
     return hipGetLastError();
 }
 
-hipError_t launch_coarse_kernel(const Geometry& g, const double* vecs, const double* tau,
-                                const bse_kernel_model& m, void* K, hipStream_t s) {
+template <bool COEF>
+static hipError_t coarse_kernel_go(const Geometry& g, const double* vecs, const double* tau,
+                                   const bse_kernel_model& m, void* K, hipStream_t s) {
     const int64_t nk = (int64_t)g.n_c * g.n_c * g.n_c;
     const int64_t npairs = nk * (nk + 1) / 2;
     const double scale = m.kernel_energy / (double)g.nk;
     if (g.dtype == BSE_F64)
-        hipLaunchKernelGGL(k_coarse_kernel<double2>, dim3((unsigned)npairs), dim3(kBlock), 0, s,
+        hipLaunchKernelGGL((k_coarse_kernel<double2, COEF>), dim3((unsigned)npairs), dim3(kBlock), 0, s,
                            reinterpret_cast<const double2*>(vecs), tau, reinterpret_cast<double2*>(K), g.n_c, g.n_div,
                            g.nv, g.nc, g.n_orb_input, m.eps_inf, m.lambda, scale, m.g2_max, m.q0_quad);
     else
-        hipLaunchKernelGGL(k_coarse_kernel<float2>, dim3((unsigned)npairs), dim3(kBlock), 0, s,
+        hipLaunchKernelGGL((k_coarse_kernel<float2, COEF>), dim3((unsigned)npairs), dim3(kBlock), 0, s,
                            reinterpret_cast<const double2*>(vecs), tau, reinterpret_cast<float2*>(K), g.n_c, g.n_div,
                            g.nv, g.nc, g.n_orb_input, m.eps_inf, m.lambda, scale, m.g2_max, m.q0_quad);
     return hipGetLastError();
+}
+
+hipError_t launch_coarse_kernel(const Geometry& g, const double* vecs, const double* tau,
+                                const bse_kernel_model& m, void* K, hipStream_t s) {
+    return coarse_kernel_go<false>(g, vecs, tau, m, K, s);
+}
+
+hipError_t launch_divergence_coefficient(const Geometry& g, const double* vecs, const double* tau,
+                                         const bse_kernel_model& m, void* A, hipStream_t s) {
+    return coarse_kernel_go<true>(g, vecs, tau, m, A, s);
 }
 
 }  // namespace bse

@@ -87,3 +87,29 @@ def test_other_entry_points_check_arguments(bse):
     assert lib.bse_build_coarse_kernel(ctypes.byref(d_big), 1, 1, ctypes.byref(m), 1, None) == bse.BSE_ERR_UNSUPPORTED
     assert lib.bse_plan_set_gemv_splits(None, 4) == bse.BSE_ERR_INVALID_ARG
     assert lib.bse_plan_set_restrict_group(None, 1) == bse.BSE_ERR_INVALID_ARG
+
+
+def test_m3_band_geometry_and_checks(bse):
+    """Band offsets |o|^2 <= (w n_div)^2 and the buffer size; widths that reach round
+    the periodic mesh, or an unsupported pair count, are rejected on the host."""
+    lib = bse.library()
+    d = bse.Dims(8, 4, 3, 6, 9, 3, bse.BSE_F32, 8)
+    n, nbytes = bse.bse_m3_band_info(d, 1.0)
+    assert n == 257
+    # table (272 padded offsets) + blocks (32768 x 272 x 18 x 18 complex FP32) + product (3 x N FP64 complex)
+    assert nbytes == 272 * 16 + 32768 * 272 * 324 * 8 + 3 * 589824 * 16
+    assert bse.bse_m3_band_info(d, 0.5)[0] == 33 and bse.bse_m3_band_info(d, 0.0)[0] == 1
+    n32 = ctypes.c_int32()
+    nb = ctypes.c_size_t()
+    assert lib.bse_m3_band_info(ctypes.byref(d), 4.0, ctypes.byref(n32), ctypes.byref(nb)) == bse.BSE_ERR_INVALID_ARG
+    assert lib.bse_m3_band_info(ctypes.byref(d), -1.0, ctypes.byref(n32), ctypes.byref(nb)) == bse.BSE_ERR_INVALID_ARG
+    small = bse.Dims(2, 2, 1, 1, 2, 1, bse.BSE_F64, 8)   # dense mesh 4: floor(w n_div) must stay below 2
+    assert lib.bse_m3_band_info(ctypes.byref(small), 1.0, ctypes.byref(n32), ctypes.byref(nb)) == bse.BSE_ERR_INVALID_ARG
+    assert lib.bse_m3_band_info(ctypes.byref(small), 0.5, ctypes.byref(n32), ctypes.byref(nb)) == bse.BSE_OK
+    m = bse.KernelModel(12.0, 0.3, 6.0, 4, 16)
+    assert lib.bse_build_m3_band(ctypes.byref(d), None, 1, ctypes.byref(m), 1.0, 256, 1 << 40, None) == bse.BSE_ERR_INVALID_ARG
+    assert lib.bse_build_m3_band(ctypes.byref(d), 1, 1, ctypes.byref(m), 1.0, 256, 16, None) == bse.BSE_ERR_WORKSPACE
+    assert lib.bse_build_m3_band(ctypes.byref(d), 1, 1, ctypes.byref(m), 1.0, 8, 1 << 40, None) == bse.BSE_ERR_WORKSPACE
+    assert lib.bse_plan_set_m3_band(None, None, 1.0) == bse.BSE_ERR_INVALID_ARG
+    assert lib.bse_build_divergence_coefficient(ctypes.byref(d), None, 1, ctypes.byref(m), 1, None) == bse.BSE_ERR_INVALID_ARG
+
