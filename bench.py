@@ -60,6 +60,8 @@ def _args():
     p.add_argument("--batch", action="store_true",
                    help="batching workload: 48 uneven Hamiltonians x 3 polarisations in one HIP graph")
     p.add_argument("--batch-launches", type=int, default=3, help="timed graph launches of the batch")
+    p.add_argument("--m3", type=float, default=None, metavar="W",
+                   help="Method 3 with band width W (units of the coarse spacing); default: Method 1")
     return p.parse_args()
 
 
@@ -94,6 +96,13 @@ def main():
     t_setup = time.perf_counter() - t0
     if args.splits:
         bse.bse_plan_set_gemv_splits(prob.plan, args.splits)
+    t_m3 = None
+    if args.m3 is not None:   # a_c and the band blocks on the device, attached to the plan
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob.set_m3(args.m3)
+        torch.cuda.synchronize()
+        t_m3 = time.perf_counter() - t0
     P = torch.as_tensor(bs.P_flat()).to("cuda").contiguous()
 
     # ---- warmup, then exactly K timed steps (one chain run of K steps)
@@ -130,6 +139,27 @@ def main():
     # products (16 columns: 4 rhs x re/im x leading/remainder)
     mfma_flops = (nbk * 4) * nbk * 4 * (2.0 * 16 * 16 * 32) if lowp else 0.0
 
+    # ---- Method 3: the band product, timed the same way
+    m3 = None
+    if args.m3 is not None:
+        prob.set_timing(2)
+        torch.cuda.synchronize()
+        prob.haydock(P, args.steps)
+        torch.cuda.synchronize()
+        band_ms_total, band_launches = prob.timing()
+        prob.set_timing(False)
+        band_ms = band_ms_total / max(1, band_launches)
+        npair = cfg.nv * cfg.nc
+        elem = 16 if dtype == "f64" else 8
+        vbytes = 16 if dtype in ("f64", "f32v64") else 8
+        # blocks once (without the padding offsets) + x once + the FP64 product written
+        band_bytes = (cfg.nk_dense * prob.m3_offsets * npair * npair * elem
+                      + n_rhs * prob.N * (vbytes + 16))
+        m3 = {"w": args.m3, "offsets": prob.m3_offsets, "band_buffer_bytes": int(prob.band.numel()),
+              "build_s": round(t_m3, 3), "band_product_avg_ms": round(band_ms, 5),
+              "band_product_launches": band_launches, "band_product_bytes": int(band_bytes),
+              "band_product_GBps": round(band_bytes / (band_ms * 1e-3) / 1e9, 1)}
+
     # ---- time to eps2 on the host from a ready plan (chain + continued fraction + copy)
     om = cfg.omega()
     torch.cuda.synchronize()
@@ -155,6 +185,8 @@ def main():
     step_bytes = (gemv_bytes + 2 * d_bytes                    # K_c; overlaps in prolong and restrict
                   + n_rhs * N * vec_bytes * 6                  # psi_i x2, psi_{i-1}, w write/read, u write
                   + N * 8)                                     # transition energies (FP64)
+    if m3 is not None:
+        step_bytes += m3["band_product_bytes"] + n_rhs * N * 16       # band blocks, x; product read back
     out = {
         "metric": "Haydock steps/s",
         "value": round(steps_per_s, 2),
@@ -172,7 +204,8 @@ def main():
         "config": {
             "workload": (f"{cfg.name}: {cfg.n_coarse}^3 coarse x {cfg.n_div}^3 divisions "
                          f"({cfg.nk_dense} dense k), {cfg.nv}v+{cfg.nc}c, N={N}, Kc {Nc}^2, "
-                         f"{n_rhs} polarisations per step, {dtype} storage, FP64 accumulation"),
+                         f"{n_rhs} polarisations per step, {dtype} storage, FP64 accumulation"
+                         + (f", Method 3 band w={args.m3}" if args.m3 is not None else "")),
             "n_coarse": cfg.n_coarse, "n_div": cfg.n_div, "nv": cfg.nv, "nc": cfg.nc, "N": N,
             "N_coarse": Nc, "polarisations": n_rhs, "parallelism": "single GPU",
         },
@@ -198,6 +231,7 @@ def main():
             "traffic": measured_traffic(args.config, dtype),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },
+        "method3": m3,
         "time_to_eps2_s": round(t_eps, 4),
         "setup_s": round(t_setup, 3),
         "inputs_s": round(t_inputs, 2),
@@ -205,7 +239,14 @@ def main():
         "eps2_peak": float(np.max(eps_host.imag)),
     }
 
-    if not args.no_cpu_baseline:
+    if m3 is not None:   # the band product is the dominant kernel of a Method 3 step
+        ach = m3["band_product_GBps"]
+        out["roofline"] = {"kernel": "Method 3 band product y = Delta x (k_m3_apply)", "bound": "hbm",
+                           "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                           "traffic_unit": "bytes per launch (not measured for this kernel)"}
+        out["coarse_product_roofline_frac"] = round(achieved_gbs / HBM_PEAK_GBS, 4)
+    if not args.no_cpu_baseline and m3 is None:
         out["cpu_baseline"] = cpu_baseline(cfg, bs, args.cpu_steps)
     prob.close()
     print(json.dumps(out), flush=True)

@@ -225,9 +225,10 @@ bse_status bse_continued_fraction(const double* a, const double* b, int32_t lda,
                                   int32_t n_omega, double eta, double* eps_re, double* eps_im,
                                   hipStream_t stream);
 
-/* Kernel timing: when enabled, the plan records HIP events around every launch
- * of the coarse product (the dominant kernel: the split product and the kernel
- * that adds its splits) on the stream it is launched on.
+/* Kernel timing: with enable = 1 the plan records HIP events around every launch
+ * of the coarse product (the dominant kernel of Method 1: the split product and
+ * the kernel that adds its splits) on the stream it is launched on; with enable = 2
+ * around every launch of the Method 3 band product instead; 0 turns timing off.
  * bse_plan_get_timing synchronises those events and returns the total time in
  * milliseconds and the number of timed launches since the last reset. */
 bse_status bse_plan_set_timing(bse_plan* plan, int32_t enable);

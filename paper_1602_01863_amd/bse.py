@@ -201,8 +201,9 @@ def bse_continued_fraction(a, b, lda, ldb, pnorm2, steps, n_chains, prefactor, o
                                        _ptr(eps_re), _ptr(eps_im), _stream(stream)), "bse_continued_fraction")
 
 
-def bse_plan_set_timing(plan, enable: bool):
-    _check(_lib.bse_plan_set_timing(plan, int(bool(enable))), "bse_plan_set_timing")
+def bse_plan_set_timing(plan, enable):
+    """enable: False / 0 off, True / 1 the coarse product, 2 the Method 3 band product."""
+    _check(_lib.bse_plan_set_timing(plan, int(enable)), "bse_plan_set_timing")
 
 
 def bse_plan_get_timing(plan):

@@ -322,7 +322,7 @@ bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d, 
     p->ws = static_cast<char*>(workspace);
     p->n_split = 0;
     p->restrict_group = 1;
-    p->timing = false;
+    p->timing = 0;
     p->ev = nullptr;
     p->ev_cap = 0;
     p->ev_used = 0;
@@ -436,7 +436,7 @@ bse_status bse_plan_set_timing(bse_plan* plan, int32_t enable) {
         p.ev_cap = cap;
     }
     if (!enable) release_events(&p);
-    p.timing = enable != 0;
+    p.timing = enable == 2 ? 2 : (enable != 0 ? 1 : 0);
     p.ev_used = 0;
     p.timed_ms = 0.0;
     p.timed_launches = 0;

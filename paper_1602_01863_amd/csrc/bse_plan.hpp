@@ -104,8 +104,8 @@ struct Plan {
     char* ws;
     int n_split;  // 0 = automatic
     int restrict_group;  // right-hand sides per restrict block (1, or 3 for three)
-    // timing of the coarse product
-    bool timing;
+    // kernel timing: 0 off, 1 the coarse product, 2 the Method 3 band product
+    int timing;
     int ev_used;
     double timed_ms;
     int64_t timed_launches;
@@ -130,7 +130,7 @@ hipError_t launch_chain_report(const Plan& p, int n_steps, double* pnorm2, int32
 bool supported_bands(int nv, int nc);
 
 // Method 3 band product y_band = Band x (m3.hip), before the prolong, which adds it
-hipError_t launch_m3_apply(const Plan& p, const void* x, int n_rhs, hipStream_t s);
+hipError_t launch_m3_apply(Plan& p, const void* x, int n_rhs, hipStream_t s);
 
 // restrict tiles from the overlaps (restrict.hip), enqueued at plan creation
 hipError_t launch_swizzle(const Plan& p, hipStream_t s);

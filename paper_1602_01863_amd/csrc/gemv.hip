@@ -465,7 +465,7 @@ static hipError_t gemv_r(Plan& p, int n_rhs, hipStream_t s) {
 
 hipError_t launch_gemv(Plan& p, int n_rhs, hipStream_t s) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (p.timing && p.ev && p.ev_used + 2 <= p.ev_cap) {
+    if (p.timing == 1 && p.ev && p.ev_used + 2 <= p.ev_cap) {
         e0 = p.ev[p.ev_used];
         e1 = p.ev[p.ev_used + 1];
         p.ev_used += 2;

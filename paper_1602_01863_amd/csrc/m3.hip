@@ -20,9 +20,11 @@
 // k_m3_apply before the prolong, which adds y (times the chain scale) to its output.
 //
 // Band buffer (caller-owned, 256-byte aligned sections):
-//   offset table  int4 [n_off_pad] (o1, o2, o3, 1); padding entries (0, 0, 0, 0)
-//   blocks        [k][chunk][n][o_local][m] in storage precision, kM3Chunk offsets
-//                 per chunk; padding offsets hold zero blocks
+//   offset table  int4 [n_off_pad] (o1, o2, o3, 1), n_off_pad = n_off rounded up to
+//                 even; a padding entry is (0, 0, 0, 0) with a zero block
+//   blocks        per k (n_off_pad np^2 entries, storage precision), chunks of
+//                 kM3Chunk offsets (the last one W <= kM3Chunk wide); inside a chunk
+//                 row n holds its W np entries (o_local, m) contiguously
 //   product       double2 [max_rhs][N]: y of the last matvec or step
 
 #include <hip/hip_runtime.h>
@@ -77,8 +79,8 @@ static bool band_layout(const Geometry& g, double w, BandLayout* L) {
         return false;
     }
     L->n_off = count_offsets(L->r, L->R2);
-    L->n_chunks = (L->n_off + kM3Chunk - 1) / kM3Chunk;
-    L->n_off_pad = L->n_chunks * kM3Chunk;
+    L->n_off_pad = (L->n_off + 1) / 2 * 2;
+    L->n_chunks = (L->n_off_pad + kM3Chunk - 1) / kM3Chunk;
     L->table = 0;
     L->blocks = up256((size_t)L->n_off_pad * sizeof(int4));
     L->yb = L->blocks + up256((size_t)g.nk * L->n_off_pad * g.np * g.np * band_elem_bytes(g.dtype));
@@ -139,7 +141,7 @@ template <class M2>
 __global__ __launch_bounds__(1024) void k_m3_band(const M2* __restrict__ d, const M2* __restrict__ acoef,
                                                   const int4* __restrict__ table, M2* __restrict__ band, int n_c,
                                                   int n_div, int nv, int nc, int neighbours, int n_off_pad,
-                                                  int n_chunks, double kappa2, double s0) {
+                                                  double kappa2, double s0) {
     __shared__ double2 dk[8][kM3MaxNE], dq[8][kM3MaxNE];
     __shared__ double2 X[kM3MaxNP * kM3MaxNP], Rb[kM3MaxNP * kM3MaxNP], Yl[kM3MaxNP * kM3MaxNP];
     __shared__ double gzz[64];
@@ -154,10 +156,11 @@ __global__ __launch_bounds__(1024) void k_m3_band(const M2* __restrict__ d, cons
     const bool act = t < np * np;
     const int row = act ? t / np : 0, col = act ? t % np : 0;
     const int chunk = o / kM3Chunk, ol = o % kM3Chunk;
-    M2* out = band + (((int64_t)k * n_chunks + chunk) * np) * (kM3Chunk * np) + ol * np;
+    const int W = min(kM3Chunk, n_off_pad - chunk * kM3Chunk);   // offsets of this chunk
+    M2* out = band + ((int64_t)k * n_off_pad + chunk * kM3Chunk) * np * np + (int64_t)ol * np;
     const int4 off = table[o];
     if (off.w == 0) {   // padding offset: zero block
-        if (act) st(out + (int64_t)row * kM3Chunk * np + col, cmake(0.0, 0.0));
+        if (act) st(out + (int64_t)row * W * np + col, cmake(0.0, 0.0));
         return;
     }
     int x[3];
@@ -249,95 +252,132 @@ __global__ __launch_bounds__(1024) void k_m3_band(const M2* __restrict__ d, cons
             }
         }
     }
-    if (act) st(out + (int64_t)row * kM3Chunk * np + col, acc);
+    if (act) st(out + (int64_t)row * W * np + col, acc);
 }
 
-// ---- product: y_k = sum_o Delta(k, k + o) x_{k+o}, one block per dense point ------------
+// ---- product: y_k = sum_o Delta(k, k + o) x_{k+o} -----------------------------------------
 //
-// Wavefront w owns rows n = w, w + 4, ... of the block row of k; its lanes stream a
-// row's entries (o, m) of one chunk as 16-byte units (one contiguous run per row and
-// chunk) and multiply them with x_{k+o}[m] staged in LDS for the chunk.  Each lane
-// accumulates in FP64; the lanes of a row are added at the end in a fixed order.
+// Every wavefront owns RG consecutive rows of the block row of one dense point k and
+// works alone (no LDS, no barrier).  Per chunk of offsets it loads its rows (one
+// contiguous run per row, 16-byte units, a lane per unit) and the x_{k+o}[m] of the
+// entries its lanes hold, straight from memory (x stays in the caches: every
+// x_{k'} serves all k of its band); the dense index of k + o is computed once per
+// chunk by the first lanes and shuffled.  The x of an entry is used by all RG rows.
+// Each lane accumulates in FP64; the lanes of a row are added at the end in a fixed
+// order.  Wavefronts are numbered so that each XCD takes a contiguous range of k.
+template <int NP>
+constexpr int m3_rows() {
+    return NP >= 3 ? 3 : NP;
+}
+
+template <class V2, int NP, int P>
+struct XPair;   // the x values of the P entries of one 16-byte unit of the band
+template <int NP>
+struct XPair<float2, NP, 2> {   // FP32 band and vectors: entries e, e + 1
+    __device__ static inline void load(const float2* x, int64_t rowbase, int e0, int kq0, int kq1, float2* out) {
+        if constexpr (NP % 2 == 0) {   // e0 even: both entries in one offset, 16 bytes
+            const f4v v = *reinterpret_cast<const f4v*>(x + rowbase + (int64_t)kq0 * NP + e0 % NP);
+            out[0] = make_float2(v.x, v.y);
+            out[1] = make_float2(v.z, v.w);
+        } else {
+            out[0] = x[rowbase + (int64_t)kq0 * NP + e0 % NP];
+            out[1] = x[rowbase + (int64_t)kq1 * NP + (e0 + 1) % NP];
+        }
+    }
+};
+template <int NP>
+struct XPair<double2, NP, 2> {   // FP32 band, FP64 vectors
+    __device__ static inline void load(const double2* x, int64_t rowbase, int e0, int kq0, int kq1, double2* out) {
+        out[0] = x[rowbase + (int64_t)kq0 * NP + e0 % NP];
+        out[1] = x[rowbase + (int64_t)kq1 * NP + (e0 + 1) % NP];
+    }
+};
+template <int NP>
+struct XPair<double2, NP, 1> {   // FP64 band and vectors: one entry per unit
+    __device__ static inline void load(const double2* x, int64_t rowbase, int e0, int kq0, int, double2* out) {
+        out[0] = x[rowbase + (int64_t)kq0 * NP + e0 % NP];
+    }
+};
+
 template <class M2, class V2, int NV, int NC, int NR>
 __global__ __launch_bounds__(256) void k_m3_apply(const M2* __restrict__ band, const int4* __restrict__ table,
                                                   const V2* __restrict__ x, double2* __restrict__ yb, int n_c,
-                                                  int n_div, int n_chunks, int64_t N) {
+                                                  int n_div, int n_off_pad, int64_t N, int64_t n_items,
+                                                  int64_t blocks_per_xcd) {
     constexpr int NP = NV * NC;
     constexpr int OC = kM3Chunk;
     using U = Unit16<M2>;
     using Rw = typename U::t;
     constexpr int P = U::P;
-    constexpr int RU = OC * NP / P;                  // 16-byte units of one row of one chunk
+    constexpr int RU = OC * NP / P;                  // 16-byte units of one row of a full chunk
     constexpr int IT = (RU + kWave - 1) / kWave;     // units per lane
-    constexpr int NW = 4;
-    constexpr int RPW = (NP + NW - 1) / NW;          // rows per wavefront
-    constexpr int NX = OC * NP * NR;                 // staged x entries per chunk
-    constexpr int XS = (NX + 255) / 256;
-    static_assert((OC * NP) % P == 0, "whole 16-byte units per row and chunk");
-    __shared__ V2 xs[NX];
-    const int64_t k = blockIdx.x;
-    const int t = threadIdx.x;
-    const int wave = t / kWave, lane = t % kWave;
+    constexpr int RG = m3_rows<NP>();
+    constexpr int NG = (NP + RG - 1) / RG;           // row groups of a block row
+    static_assert((2 * NP) % P == 0 && (OC * NP) % P == 0, "whole 16-byte units per row and chunk");
+    static_assert(OC <= kWave, "one lane per offset of a chunk");
+    const int64_t blk = (int64_t)(blockIdx.x % 8) * blocks_per_xcd + blockIdx.x / 8;
+    const int64_t item = blk * 4 + threadIdx.x / kWave;
+    if (item >= n_items) return;   // whole wavefront; the kernel has no barrier
+    const int64_t k = item / NG;
+    const int g = (int)(item % NG);
+    const int lane = threadIdx.x % kWave;
     int xk[3];
     dense_coords(k, n_c, n_div, xk);
-    const Rw* bk = reinterpret_cast<const Rw*>(band) + (int64_t)k * n_chunks * NP * RU;
+    const Rw* bk = reinterpret_cast<const Rw*>(band) + (int64_t)k * n_off_pad * NP * NP / P;
 
-    cd acc[RPW][NR];
+    cd acc[RG][NR];
 #pragma unroll
-    for (int rr = 0; rr < RPW; ++rr)
+    for (int rr = 0; rr < RG; ++rr)
 #pragma unroll
         for (int r = 0; r < NR; ++r) acc[rr][r] = cmake(0.0, 0.0);
 
-    for (int ch = 0; ch < n_chunks; ++ch) {
-        // all loads of the chunk first: the wavefront's block rows and the x values
-        Rw bu[RPW][IT];
-#pragma unroll
-        for (int rr = 0; rr < RPW; ++rr) {
-            const int n = min(wave + rr * NW, NP - 1);
-#pragma unroll
-            for (int it = 0; it < IT; ++it) bu[rr][it] = bk[((int64_t)ch * NP + n) * RU + min(lane + it * kWave, RU - 1)];
-        }
-        V2 xv[XS];
-#pragma unroll
-        for (int q = 0; q < XS; ++q) {
-            const int i = min(t + q * 256, NX - 1);
-            const int r = i % NR, m = (i / NR) % NP, ol = i / (NR * NP);
-            const int4 o = table[ch * OC + ol];
+    for (int c0 = 0; c0 < n_off_pad; c0 += OC) {
+        const int ru = min(OC, n_off_pad - c0) * NP / P;   // units of one row of this chunk
+        const Rw* bc = bk + (int64_t)c0 * NP * NP / P;
+        // dense index of k + o for the chunk's offsets (lane l < OC holds offset c0 + l)
+        int kq_l;
+        {
+            const int4 o = table[min(c0 + lane, n_off_pad - 1)];
             const int xq[3] = {xk[0] + o.x, xk[1] + o.y, xk[2] + o.z};
-            xv[q] = x[(int64_t)r * N + dense_index(xq, n_c, n_div) * NP + m];
+            kq_l = (int)dense_index(xq, n_c, n_div);
+        }
+        Rw bu[RG][IT];
+#pragma unroll
+        for (int rr = 0; rr < RG; ++rr) {
+            const int n = min(g * RG + rr, NP - 1);
+#pragma unroll
+            for (int it = 0; it < IT; ++it) bu[rr][it] = bc[(int64_t)n * ru + min(lane + it * kWave, ru - 1)];
+        }
+        V2 xv[IT][NR][P];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e0 = min(lane + it * kWave, ru - 1) * P;
+            const int kq0 = __shfl(kq_l, e0 / NP, kWave);
+            const int kq1 = __shfl(kq_l, min((e0 + P - 1) / NP, OC - 1), kWave);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) XPair<V2, NP, P>::load(x, (int64_t)r * N, e0, kq0, kq1, xv[it][r]);
         }
         __builtin_amdgcn_sched_barrier(0);
-        __syncthreads();   // the previous chunk's readers of xs are done
 #pragma unroll
-        for (int q = 0; q < XS; ++q)
-            if (t + q * 256 < NX) xs[t + q * 256] = xv[q];
-        __syncthreads();
+        for (int it = 0; it < IT; ++it) {
+            if (lane + it * kWave >= ru) break;
 #pragma unroll
-        for (int rr = 0; rr < RPW; ++rr) {
-            if (wave + rr * NW >= NP) break;   // uniform per wavefront
+            for (int pp = 0; pp < P; ++pp)
 #pragma unroll
-            for (int it = 0; it < IT; ++it) {
-                const int u = lane + it * kWave;
-                if (u >= RU) break;
-#pragma unroll
-                for (int pp = 0; pp < P; ++pp) {
-                    const int e = u * P + pp;
-                    const int ol = e / NP, m = e % NP;
+                for (int rr = 0; rr < RG; ++rr) {
                     const cd bv = cv(U::get(bu[rr][it], pp));
 #pragma unroll
-                    for (int r = 0; r < NR; ++r) cfma(acc[rr][r], bv, cv(xs[(ol * NP + m) * NR + r]));
+                    for (int r = 0; r < NR; ++r) cfma(acc[rr][r], bv, cv(xv[it][r][pp]));
                 }
-            }
         }
     }
 #pragma unroll
-    for (int rr = 0; rr < RPW; ++rr) {
-        const int n = wave + rr * NW;
-        if (n >= NP) break;
+    for (int rr = 0; rr < RG; ++rr) {
+        const int n = g * RG + rr;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const double re = wave_sum(acc[rr][r].re), im = wave_sum(acc[rr][r].im);
-            if (lane == 0) yb[(int64_t)r * N + k * NP + n] = make_double2(re, im);
+            if (lane == 0 && n < NP) yb[(int64_t)r * N + k * NP + n] = make_double2(re, im);
         }
     }
 }
@@ -348,14 +388,21 @@ static hipError_t m3_apply_go(const Plan& p, const void* x, int n_rhs, hipStream
     const M2* band = reinterpret_cast<const M2*>(p.m3_band + up256((size_t)p.m3_noff_pad * sizeof(int4)));
     const int4* table = reinterpret_cast<const int4*>(p.m3_band);
     const V2* xv = reinterpret_cast<const V2*>(x);
-    const int n_chunks = p.m3_noff_pad / kM3Chunk;
-    dim3 grid((unsigned)g.nk), block(256);
+    constexpr int NP = NV * NC;
+    const int64_t n_items = g.nk * ((NP + m3_rows<NP>() - 1) / m3_rows<NP>());   // (k, row group) wavefronts
+    const int64_t nblk = (n_items + 3) / 4;
+    const int64_t per_xcd = (nblk + 7) / 8;
+    dim3 grid((unsigned)(8 * per_xcd)), block(256);
+#define BSE_M3_GO(R)                                                                                              \
+    hipLaunchKernelGGL((k_m3_apply<M2, V2, NV, NC, R>), grid, block, 0, s, band, table, xv, p.m3_yb, g.n_c, g.n_div, \
+                       p.m3_noff_pad, g.N, n_items, per_xcd)
     switch (n_rhs) {
-        case 1: hipLaunchKernelGGL((k_m3_apply<M2, V2, NV, NC, 1>), grid, block, 0, s, band, table, xv, p.m3_yb, g.n_c, g.n_div, n_chunks, g.N); break;
-        case 2: hipLaunchKernelGGL((k_m3_apply<M2, V2, NV, NC, 2>), grid, block, 0, s, band, table, xv, p.m3_yb, g.n_c, g.n_div, n_chunks, g.N); break;
-        case 3: hipLaunchKernelGGL((k_m3_apply<M2, V2, NV, NC, 3>), grid, block, 0, s, band, table, xv, p.m3_yb, g.n_c, g.n_div, n_chunks, g.N); break;
-        default: hipLaunchKernelGGL((k_m3_apply<M2, V2, NV, NC, 4>), grid, block, 0, s, band, table, xv, p.m3_yb, g.n_c, g.n_div, n_chunks, g.N); break;
+        case 1: BSE_M3_GO(1); break;
+        case 2: BSE_M3_GO(2); break;
+        case 3: BSE_M3_GO(3); break;
+        default: BSE_M3_GO(4); break;
     }
+#undef BSE_M3_GO
     return hipGetLastError();
 }
 
@@ -370,14 +417,23 @@ static hipError_t m3_apply_dt(const Plan& p, const void* x, int n_rhs, hipStream
     }
 }
 
-hipError_t launch_m3_apply(const Plan& p, const void* x, int n_rhs, hipStream_t s) {
+hipError_t launch_m3_apply(Plan& p, const void* x, int n_rhs, hipStream_t s) {
     if (!p.m3_band) return hipSuccess;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (p.timing == 2 && p.ev && p.ev_used + 2 <= p.ev_cap) {
+        e0 = p.ev[p.ev_used];
+        e1 = p.ev[p.ev_used + 1];
+        p.ev_used += 2;
+        (void)hipEventRecord(e0, s);
+    }
+    hipError_t err = hipErrorInvalidValue;
     const int nv = p.g.nv, nc = p.g.nc;
 #define BSE_CASE(a_, b_) \
-    if (nv == a_ && nc == b_) return m3_apply_dt<a_, b_>(p, x, n_rhs, s);
+    if (nv == a_ && nc == b_) err = m3_apply_dt<a_, b_>(p, x, n_rhs, s);
     BSE_BANDS(BSE_CASE)
 #undef BSE_CASE
-    return hipErrorInvalidValue;
+    if (e1) (void)hipEventRecord(e1, s);
+    return err;
 }
 
 }  // namespace bse
@@ -447,12 +503,12 @@ bse_status bse_build_m3_band(const bse_dims* dims, const void* d, const void* a_
             hipLaunchKernelGGL(k_m3_band<double2>, grid, dim3(threads), 0, stream, reinterpret_cast<const double2*>(d),
                                reinterpret_cast<const double2*>(a_coef), table,
                                reinterpret_cast<double2*>(base + L.blocks), g.n_c, g.n_div, g.nv, g.nc, g.neighbours,
-                               L.n_off_pad, L.n_chunks, kappa2, s0);
+                               L.n_off_pad, kappa2, s0);
         else
             hipLaunchKernelGGL(k_m3_band<float2>, grid, dim3(threads), 0, stream, reinterpret_cast<const float2*>(d),
                                reinterpret_cast<const float2*>(a_coef), table,
                                reinterpret_cast<float2*>(base + L.blocks), g.n_c, g.n_div, g.nv, g.nc, g.neighbours,
-                               L.n_off_pad, L.n_chunks, kappa2, s0);
+                               L.n_off_pad, kappa2, s0);
         e = hipGetLastError();
     }
     return e == hipSuccess ? BSE_OK : hip_fail_status(e, "bse_build_m3_band");

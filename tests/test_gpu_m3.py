@@ -42,16 +42,23 @@ def _oracle_m3(cfg, weights="trilinear"):
 
 
 def _gpu_blocks(prob, n_off):
-    """Library band buffer -> [N_k, n_off, np, np] complex128."""
+    """Library band buffer -> [N_k, n_off, np, np] complex128.  Layout: per k, chunks
+    of CHUNK offsets (the last one narrower; offsets padded to an even count), and
+    inside a chunk of width W, row n holds its W np entries (o_local, m)."""
     npair = prob.dims.nv * prob.dims.nc
-    n_pad = (n_off + CHUNK - 1) // CHUNK * CHUNK
+    n_pad = (n_off + 1) // 2 * 2
     start = (n_pad * 16 + 255) // 256 * 256
     esz = 16 if prob.mat_dtype == torch.complex128 else 8
     nbytes = prob.nk * n_pad * npair * npair * esz
     raw = prob.band[start:start + nbytes].cpu().numpy()
     arr = raw.view(np.complex128 if esz == 16 else np.complex64).astype(np.complex128)
-    arr = arr.reshape(prob.nk, n_pad // CHUNK, npair, CHUNK, npair)
-    return arr.transpose(0, 1, 3, 2, 4).reshape(prob.nk, n_pad, npair, npair)[:, :n_off]
+    arr = arr.reshape(prob.nk, n_pad * npair * npair)
+    out = np.empty((prob.nk, n_pad, npair, npair), dtype=np.complex128)
+    for c0 in range(0, n_pad, CHUNK):
+        W = min(CHUNK, n_pad - c0)
+        chunk = arr[:, c0 * npair * npair:(c0 + W) * npair * npair].reshape(prob.nk, npair, W, npair)
+        out[:, c0:c0 + W] = chunk.transpose(0, 2, 1, 3)
+    return out[:, :n_off]
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])

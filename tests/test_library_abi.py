@@ -96,8 +96,9 @@ def test_m3_band_geometry_and_checks(bse):
     d = bse.Dims(8, 4, 3, 6, 9, 3, bse.BSE_F32, 8)
     n, nbytes = bse.bse_m3_band_info(d, 1.0)
     assert n == 257
-    # table (272 padded offsets) + blocks (32768 x 272 x 18 x 18 complex FP32) + product (3 x N FP64 complex)
-    assert nbytes == 272 * 16 + 32768 * 272 * 324 * 8 + 3 * 589824 * 16
+    # table (258 offsets, padded to even, rounded to 256 bytes) + blocks (32768 x 258 x 18 x 18
+    # complex FP32) + product (3 x N FP64 complex)
+    assert nbytes == 4352 + 32768 * 258 * 324 * 8 + 3 * 589824 * 16
     assert bse.bse_m3_band_info(d, 0.5)[0] == 33 and bse.bse_m3_band_info(d, 0.0)[0] == 1
     n32 = ctypes.c_int32()
     nb = ctypes.c_size_t()
