@@ -198,3 +198,37 @@ def test_m3_operator_hermitian_at_full_size(bse):
     assert np.all(np.abs(lhs - rhs) < 1e-5 * mag)
     assert rel_l2(hx, h1x) > 1e-4
     prob.close()
+
+
+@pytest.mark.parametrize("n_c,dtype,steps", [(4, "f64", 200), (8, "f32", 400)], ids=["4^3x2", "8^3x2"])
+def test_library_m3_closer_than_m1_to_the_dense_mesh(bse, n_c, dtype, steps):
+    """The comparison of Sec. 5 through the library: eps2 from M1 and from M3 (w = 1)
+    on an n_c^3 x 2 double grid against the BSE built directly on the (2 n_c)^3 dense
+    mesh (one division: no interpolation; 36 864 transitions for n_c = 8, a 10.9 GB
+    kernel).  Chains of `steps` steps, eta = 0.2 eV; C0 crystal (seed 0, 3v3c)."""
+    import time
+    cfg = ti.get_config("c0").with_(n_coarse=n_c, steps=steps)
+    cfg_d = cfg.with_(n_coarse=2 * n_c, n_div=1)
+    om, C, eta = cfg.omega(), cfg.prefactor(), 0.2
+    assert abs(cfg_d.prefactor() - C) < 1e-15 * C
+    out = {}
+    for name, c, w in (("dense", cfg_d, None), ("M1", cfg, None), ("M3", cfg, 1.0)):
+        bs = bands(c)
+        prob = bse.problem_from_bands(bs, c, dtype=dtype, max_rhs=1)
+        if w is not None:
+            prob.set_m3(w)
+        P = bs.P_flat()[:1]
+        prob.haydock(P, 5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch = prob.haydock(P, steps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        assert int(ch["status"][0]) == bse.BSE_OK
+        out[name] = (prob.continued_fraction(ch, C, om, eta).cpu().numpy().imag[0], dt)
+        prob.close()
+    ref = out["dense"][0]
+    e1, e3 = rel_l2(out["M1"][0], ref), rel_l2(out["M3"][0], ref)
+    print(f"\n{n_c}^3 x 2 ({dtype}): eps2 error vs dense mesh M1 {e1:.4f} M3 {e3:.4f}; ms/step dense "
+          f"{1e3 * out['dense'][1]:.3f} M1 {1e3 * out['M1'][1]:.3f} M3 {1e3 * out['M3'][1]:.3f}")
+    assert e3 < 0.7 * e1
