@@ -60,6 +60,9 @@ def _args():
     p.add_argument("--batch", action="store_true",
                    help="batching workload: 48 uneven Hamiltonians x 3 polarisations in one HIP graph")
     p.add_argument("--batch-launches", type=int, default=3, help="timed graph launches of the batch")
+    p.add_argument("--time-to-spectrum", action="store_true",
+                   help="time to eps2 of the plain FP32 form against the BF16 form, its graph-recorded "
+                        "chains and the learned terminator (C1 workload)")
     p.add_argument("--m3", type=float, default=None, metavar="W",
                    help="Method 3 with band width W (units of the coarse spacing); default: Method 1")
     return p.parse_args()
@@ -81,6 +84,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.batch:
         batch_bench(args)
+        return
+    if args.time_to_spectrum:
+        spectrum_race(args)
         return
     cfg = ti.get_config(args.config)
     dtype = args.dtype or {"c128": "f64", "c64": "f32"}[cfg.dtype]
@@ -332,6 +338,73 @@ def batch_bench(args):
     for p in probs:
         p.close()
     print(json.dumps(out), flush=True)
+
+
+def spectrum_race(args):
+    """Time from a ready plan to eps2 on the host (chains, continued fraction, copy) on
+    the headline workload, for the plain FP32 form and for the BF16 form alone, with its
+    chains recorded into a HIP graph, and closed by the learned terminator (64 steps,
+    the full plain chain when the error estimate exceeds 1e-3).  Each eps2 is compared
+    with the plain FP32 one (relative L2), at the workload's broadening and two wider
+    ones.  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import tbinputs as ti
+    from paper_1602_01863_amd import bse
+    from paper_1602_01863_amd import terminator as T
+
+    cfg = ti.get_config(args.config)
+    bs = ti.band_structure(cfg)
+    om, C, steps = cfg.omega(), cfg.prefactor(), cfg.steps
+    etas = (cfg.eta, 0.2, 0.5)
+    P = torch.as_tensor(bs.P_flat()).to("cuda").contiguous()
+    probs = {dt: bse.problem_from_bands(bs, cfg, dtype=dt, max_rhs=cfg.n_pol) for dt in ("f32", "bf16")}
+    graph = bse.BSEBatch([probs["bf16"]], [P], steps, n_branches=1)
+    net = T.TerminatorMLP.load(T.default_weights_path())
+
+    def eps2(prob, ch, eta):
+        return prob.continued_fraction(ch, C, om, eta).cpu().numpy().imag
+
+    forms = {
+        "f32": lambda eta: (eps2(probs["f32"], probs["f32"].haydock(P, steps), eta), None),
+        "bf16": lambda eta: (eps2(probs["bf16"], probs["bf16"].haydock(P, steps), eta), None),
+        "bf16_graph": lambda eta: (eps2(probs["bf16"], graph.run()[0], eta), None),
+        "bf16_terminator": lambda eta: _terminated(T, probs["bf16"], P, net, steps, C, om, eta),
+    }
+    out_forms = {}
+    ref = {}
+    for name, fn in forms.items():
+        fn(etas[0])   # warm
+        rows = {}
+        for eta in etas:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e, fb = fn(eta)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if name == "f32":
+                ref[eta] = e
+            err = float(np.linalg.norm(e - ref[eta]) / np.linalg.norm(ref[eta]))
+            rows[str(eta)] = {"s": round(dt, 4), "eps2_rel_err_vs_f32": err}
+            if fb is not None:
+                rows[str(eta)]["fallback_fraction"] = float(np.mean(fb))
+        out_forms[name] = rows
+    graph.close()
+    for p in probs.values():
+        p.close()
+    out = {"metric": "time to eps2 from a ready plan", "unit": "s", "higher_is_better": False, "n_gpus": 1,
+           "data": "synthetic (seeded tight-binding crystal)",
+           "config": {"workload": f"{cfg.name}: {cfg.n_coarse}^3 x {cfg.n_div}, {cfg.nv}v{cfg.nc}c, N={cfg.n_trans}, "
+                                  f"{steps} steps x {cfg.n_pol} polarisations, {cfg.n_omega} omega points"},
+           "forms": out_forms}
+    print(json.dumps(out), flush=True)
+
+
+def _terminated(T, prob, P, net, steps, C, om, eta):
+    """eps2 closed by the terminator after 64 steps, with the full-chain fallback."""
+    eps, fb = T.run_with_fallback(prob, P, net, steps, C, om, eta, threshold=1e-3)
+    return eps.imag, fb
 
 
 def cpu_baseline(cfg, bs, n_steps):
