@@ -96,6 +96,18 @@ size_t lds_limit() {
     }
     return cache[dev];
 }
+int cu_count() {
+    // compute units of the current device (queried once per device)
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cache[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        cache[dev] = v;
+    }
+    return cache[dev];
+}
 static size_t vec_elem_bytes(int dtype) { return vec_is_f32(dtype) ? sizeof(float2) : sizeof(double2); }
 static size_t mat_elem_bytes(int dtype) { return dtype == BSE_F64 ? sizeof(double2) : sizeof(float2); }
 

@@ -180,5 +180,7 @@ hipError_t enqueue_haydock(Plan& p, const double* P, int n_rhs, int n_steps, dou
 bse_status hip_fail_status(hipError_t e, const char* what);
 // bytes of shared memory (static + dynamic) one block may use on the current device
 size_t lds_limit();
+// compute units of the current device
+int cu_count();
 
 }  // namespace bse

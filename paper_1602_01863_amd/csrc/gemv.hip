@@ -198,15 +198,29 @@ __global__ __launch_bounds__(256) void k_gemv_reduce(const double2* __restrict__
     rout[o] = make_double2(re, im);
 }
 
-static void gemv_shape(const Plan& p, int rw, int* n_rowblk, int* n_split, int* col_chunk) {
+// Automatic column splits: at least 2048 blocks, except that a product whose columns
+// can all be staged at once (single-stage blocks) takes the splits that make one round
+// of resident blocks (4 per compute unit) if that round is at least 85% full: every
+// block starts at once and no small last round is left as a tail (measured: C1 FP32
+// 0.214 -> 0.209 ms per step; blocks that stage their columns in pieces did better
+// with more of them).
+static int auto_splits(int n_rowblk, int single_stage_cols, int Nc) {
+    const int resident = 4 * cu_count();
+    const int ns1 = resident / n_rowblk;
+    if (ns1 >= 1 && (double)ns1 * n_rowblk >= 0.85 * resident && (Nc + ns1 - 1) / ns1 <= single_stage_cols)
+        return ns1;
+    return (2048 + n_rowblk - 1) / n_rowblk;
+}
+
+static void gemv_shape(const Plan& p, int rw, int nrhs, int* n_rowblk, int* n_split, int* col_chunk) {
     const int Nc = (int)p.g.Nc;
     *n_rowblk = (Nc + rw - 1) / rw;
     int ns = p.n_split;
-    if (ns <= 0) ns = (2048 + *n_rowblk - 1) / *n_rowblk;
+    if (ns <= 0) ns = auto_splits(*n_rowblk, kGemvLdsCols / nrhs - 4, Nc);
     ns = std::max(1, std::min(ns, kMaxSplit));
     ns = std::min(ns, std::max(1, Nc / 32));
     int chunk = (Nc + ns - 1) / ns;
-    chunk = (chunk + 31) / 32 * 32;
+    chunk = (chunk + 3) / 4 * 4;   // whole columns per wavefront of a block
     *col_chunk = chunk;
     *n_split = (Nc + chunk - 1) / chunk;
 }
@@ -216,7 +230,7 @@ static hipError_t gemv_t(Plan& p, hipStream_t s) {
     const Geometry& g = p.g;
     constexpr int RW = kWave * Gv<M2>::E;
     int n_rowblk, n_split, chunk;
-    gemv_shape(p, RW, &n_rowblk, &n_split, &chunk);
+    gemv_shape(p, RW, NRHS, &n_rowblk, &n_split, &chunk);
     const size_t lds =
         std::max((size_t)std::min(chunk, kGemvLdsCols / NRHS) * NRHS, (size_t)3 * kWave * Gv<M2>::E * NRHS) *
         sizeof(double2);
