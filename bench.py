@@ -60,6 +60,7 @@ def _args():
     p.add_argument("--batch", action="store_true",
                    help="batching workload: 48 uneven Hamiltonians x 3 polarisations in one HIP graph")
     p.add_argument("--batch-launches", type=int, default=3, help="timed graph launches of the batch")
+    p.add_argument("--no-autotune", action="store_true", help="batch: keep the automatic tunables")
     p.add_argument("--time-to-spectrum", action="store_true",
                    help="time to eps2 of the plain FP32 form against the BF16 form, its graph-recorded "
                         "chains and the learned terminator (C1 workload)")
@@ -284,6 +285,8 @@ def batch_bench(args):
     t0 = time.perf_counter()
     tuned = {}
     for c, p, P in zip(cfgs, probs, Ps):
+        if args.no_autotune:
+            break
         key = (c.n_coarse, c.n_div, c.nc)
         if key not in tuned:
             tuned[key] = autotune(p, P, steps=10, repeats=2)
@@ -301,7 +304,8 @@ def batch_bench(args):
         p.haydock(P, steps)
     torch.cuda.synchronize()
     t_eager = time.perf_counter() - t0
-    batch = bse.BSEBatch(probs, Ps, steps, n_branches=4)
+    n_branches = bse.default_branches()
+    batch = bse.BSEBatch(probs, Ps, steps, n_branches=n_branches)
     batch.run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -323,10 +327,10 @@ def batch_bench(args):
         "config": {"workload": f"batching: {len(cfgs)} Hamiltonians x 3 polarisations = {n_chains} chains "
                                f"of {steps} steps (grids 4^3x2, 6^3x3, 8^3x4; nv 3, nc 3 or 6)",
                    "hamiltonians": len(cfgs), "chains": n_chains, "steps": steps,
-                   "transitions_total": int(sum(p.N for p in probs)), "graph_branches": 4},
+                   "transitions_total": int(sum(p.N for p in probs)), "graph_branches": n_branches},
         "batch_s": round(t_batch, 4),
         "per_chain_steps_per_s": round(steps / t_batch, 1),
-        "graph_launches_per_batch": 1,
+        "graph_launches_per_batch": n_branches,
         "kernel_launches_per_batch_without_graph": int(sum(3 + 5 * steps for _ in probs)),
         "sequential_host_launched_s": round(t_eager, 4),
         "speedup_vs_sequential": round(t_eager / t_batch, 3),

@@ -243,6 +243,18 @@ def bse_batch_destroy(batch):
     _lib.bse_batch_destroy(batch)
 
 
+def default_branches() -> int:
+    """Branches of a batch: one per hardware queue the runtime gives this process
+    (GPU_MAX_HW_QUEUES, 4 by default), less the one the caller's stream keeps.  With
+    more branches than that, two branch streams can share a hardware queue and run one
+    after the other (measured: 48-member batch 0.74 s with 4 branches, 0.67 s with 3)."""
+    try:
+        queues = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+    except ValueError:
+        queues = 4
+    return max(1, min(16, queues - 1))
+
+
 class BSEBatch:
     """Haydock chains of many problems recorded into HIP graphs, one per branch (bse_batch_*).
 
@@ -251,7 +263,9 @@ class BSEBatch:
     all chains and leaves them in .chains (one dict per problem, as BSEProblem.haydock).
     """
 
-    def __init__(self, problems, P_list, n_steps: int, n_branches: int = 4):
+    def __init__(self, problems, P_list, n_steps: int, n_branches: int | None = None):
+        if n_branches is None:
+            n_branches = default_branches()
         self.problems = list(problems)
         self.P = []
         self.chains = []
