@@ -232,3 +232,30 @@ def test_library_m3_closer_than_m1_to_the_dense_mesh(bse, n_c, dtype, steps):
     print(f"\n{n_c}^3 x 2 ({dtype}): eps2 error vs dense mesh M1 {e1:.4f} M3 {e3:.4f}; ms/step dense "
           f"{1e3 * out['dense'][1]:.3f} M1 {1e3 * out['M1'][1]:.3f} M3 {1e3 * out['M3'][1]:.3f}")
     assert e3 < 0.7 * e1
+
+
+@pytest.mark.parametrize("w", [0.0, 1.5], ids=["diagonal_only", "widest"])
+def test_m3_band_edge_widths(bse, w):
+    """w = 0: the band is the diagonal block alone (one offset, padded to two with a
+    zero block); w = 1.5 on the 8^3 dense mesh of C0: 123 offsets, the widest band
+    that does not reach round the mesh (2 floor(w n_div) = 6 < 8), several full
+    chunks and a short last one.  FP64 matvec against the explicit kernel."""
+    cfg = ti.get_config("c0")
+    op, a, Sc, k2, s0 = _oracle_m3(cfg)
+    K3 = O.m3.explicit_kernel(op, a, Sc, w, k2, s0)
+    prob = bse.problem_from_bands(bands(cfg), cfg, dtype="f64", max_rhs=1)
+    prob.set_m3(w)
+    assert prob.m3_offsets == len(O.m3.band_offsets(cfg.n_div, w))
+    x = ti.random_vectors(op.N, 1, 77)
+    y = prob.matvec(x).cpu().numpy()
+    ref = op.delta[None, :] * x + (K3 @ x.T).T
+    assert rel_l2(y, ref) < 1e-13
+    prob.close()
+
+
+def test_m3_rejects_a_band_that_wraps(bse):
+    cfg = ti.get_config("c0")
+    prob = bse.problem_from_bands(bands(cfg), cfg, dtype="f64", max_rhs=1)
+    with pytest.raises(bse.BSEError):
+        prob.set_m3(2.0)   # 2 floor(w n_div) = 8 reaches the 8^3 dense mesh
+    prob.close()
