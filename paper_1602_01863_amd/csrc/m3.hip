@@ -265,9 +265,15 @@ __global__ __launch_bounds__(1024) void k_m3_band(const M2* __restrict__ d, cons
 // chunk by the first lanes and shuffled.  The x of an entry is used by all RG rows.
 // Each lane accumulates in FP64; the lanes of a row are added at the end in a fixed
 // order.  Wavefronts are numbered so that each XCD takes a contiguous range of k.
-template <int NP>
+// Rows per wavefront: the x of an entry serves all of them, so more rows cut the
+// cache traffic of x (measured on 8^3 x 4, 3v6c, w = 1: 3 rows 4.9 TB/s, 6 rows 5.8 TB/s,
+// no x loads at all 6.1 TB/s).  Up to 6 rows for FP32 blocks, balanced over the groups;
+// 3 for FP64 blocks, whose 16-byte units hold one entry and need more registers.
+template <int NP, int P>
 constexpr int m3_rows() {
-    return NP >= 3 ? 3 : NP;
+    constexpr int cap = P == 2 ? 6 : 3;
+    constexpr int groups = (NP + cap - 1) / cap;
+    return (NP + groups - 1) / groups;
 }
 
 template <class V2, int NP, int P>
@@ -311,7 +317,7 @@ __global__ __launch_bounds__(256) void k_m3_apply(const M2* __restrict__ band, c
     constexpr int P = U::P;
     constexpr int RU = OC * NP / P;                  // 16-byte units of one row of a full chunk
     constexpr int IT = (RU + kWave - 1) / kWave;     // units per lane
-    constexpr int RG = m3_rows<NP>();
+    constexpr int RG = m3_rows<NP, P>();
     constexpr int NG = (NP + RG - 1) / RG;           // row groups of a block row
     static_assert((2 * NP) % P == 0 && (OC * NP) % P == 0, "whole 16-byte units per row and chunk");
     static_assert(OC <= kWave, "one lane per offset of a chunk");
@@ -389,7 +395,8 @@ static hipError_t m3_apply_go(const Plan& p, const void* x, int n_rhs, hipStream
     const int4* table = reinterpret_cast<const int4*>(p.m3_band);
     const V2* xv = reinterpret_cast<const V2*>(x);
     constexpr int NP = NV * NC;
-    const int64_t n_items = g.nk * ((NP + m3_rows<NP>() - 1) / m3_rows<NP>());   // (k, row group) wavefronts
+    constexpr int RG = m3_rows<NP, Unit16<M2>::P>();
+    const int64_t n_items = g.nk * ((NP + RG - 1) / RG);   // (k, row group) wavefronts
     const int64_t nblk = (n_items + 3) / 4;
     const int64_t per_xcd = (nblk + 7) / 8;
     dim3 grid((unsigned)(8 * per_xcd)), block(256);
