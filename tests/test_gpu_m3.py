@@ -259,3 +259,25 @@ def test_m3_rejects_a_band_that_wraps(bse):
     with pytest.raises(bse.BSEError):
         prob.set_m3(2.0)   # 2 floor(w n_div) = 8 reaches the 8^3 dense mesh
     prob.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32v64", "bf16"])
+def test_m3_with_other_storage_forms(bse, dtype):
+    """The band with FP64 Lanczos vectors (FP32 band blocks, FP64 x) and with the
+    block-scaled BF16 coarse kernel (FP32 band blocks): relative L2 against the FP64
+    oracle within the storage form's rounding (FP32: 1e-6; BF16 kernel: 2 BF16 units on
+    the whole product)."""
+    cfg = ti.tiny_config(n_coarse=3, n_div=2, nv=3, nc=6, n_orb=9, seed=21, n_pol=3)
+    op, a, Sc, k2, s0 = _oracle_m3(cfg)
+    off = O.m3.band_offsets(cfg.n_div, 1.0)
+    blocks = O.m3.band_blocks(op, a, Sc, off, O.m3.dense_shape(off, cfg.n_coarse, cfg.n_div, k2, s0))
+    x = ti.random_vectors(op.N, 3, 88)
+    x = x / np.linalg.norm(x, axis=1, keepdims=True)
+    prob = bse.problem_from_bands(bands(cfg), cfg, dtype=dtype, max_rhs=3)
+    prob.set_m3(1.0)
+    xs = prob.vector(x)
+    y = prob.matvec(xs).cpu().numpy().astype(np.complex128)
+    ref = O.m3.apply(op, blocks, off, xs.cpu().numpy().astype(np.complex128))
+    tol = 1e-6 if dtype == "f32v64" else 2 * 2.0 ** -8
+    assert rel_l2(y, ref) < tol
+    prob.close()
