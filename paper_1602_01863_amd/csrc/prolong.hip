@@ -122,10 +122,11 @@ __global__ __launch_bounds__(256) void k_prolong1(const M2* __restrict__ d, cons
 // sit in an LDS table; the diagonal, the -b_i psi_{i-1} term and the chain partials
 // are applied after the corner loop, so psi_i is read once.
 // wavefronts per SIMD the register budget allows: 3 (<= 168 VGPRs) where the
-// FP32-storage variant fits without spills, else 2
-template <class M2, int NV, int NC>
+// FP32-storage variant fits without spills (FP32 vectors, up to three right-hand
+// sides), else 2
+template <class M2, class V2, int NV, int NC, int NR>
 constexpr int prolong3_waves() {
-    return (sizeof(M2) == 8 && NV * NC <= 18 && !(NV == 3 && NC == 4)) ? 3 : 2;
+    return (sizeof(M2) == 8 && sizeof(V2) == 8 && NV * NC <= 18 && !(NV == 3 && NC == 4) && NR < 4) ? 3 : 2;
 }
 
 // threads of a block: 2 wavefronts per right-hand side, at least 4 wavefronts (the
@@ -136,7 +137,7 @@ constexpr int prolong3_threads() {
 }
 
 template <class M2, class V2, int NV, int NC, int MODE, int NR>
-__global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, NV, NC>())) void k_prolong3(const M2* __restrict__ d, const double* __restrict__ delta,
+__global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, V2, NV, NC, NR>())) void k_prolong3(const M2* __restrict__ d, const double* __restrict__ delta,
                                                          const double2* __restrict__ rvec, const V2* __restrict__ x,
                                                          V2* __restrict__ out, double* __restrict__ ppart,
                                                          const ChainState* __restrict__ chain, int n_c, int n_div,
