@@ -334,6 +334,8 @@ def batch_bench(args):
         "kernel_launches_per_batch_without_graph": int(sum(3 + 5 * steps for _ in probs)),
         "sequential_host_launched_s": round(t_eager, 4),
         "speedup_vs_sequential": round(t_eager / t_batch, 3),
+        "roofline": batch_roofline(cfgs, probs, steps, t_batch),
+        "cpu_baseline": None if args.no_cpu_baseline else batch_cpu_baseline(cfgs, bss, steps),
         "chain_status": status,
         "autotuned": shapes,
         "inputs_s": round(t_inputs, 1), "setup_s": round(t_setup, 2), "tune_s": round(t_tune, 2),
@@ -342,6 +344,54 @@ def batch_bench(args):
     for p in probs:
         p.close()
     print(json.dumps(out), flush=True)
+
+
+def batch_roofline(cfgs, probs, steps, t_batch):
+    """Aggregate algorithmic HBM bytes of every member's steps (K_c once, the overlaps
+    in prolong and restrict, the Lanczos vectors, the transition energies) over the
+    batch time, against the HBM peak."""
+    total = 0.0
+    for c, p in zip(cfgs, probs):
+        ne = c.nv ** 2 + c.nc ** 2
+        d_bytes = c.nk_coarse * 8 * ne * c.n_div3 * 8
+        step = p.Nc * p.Nc * 8 + 2 * p.Nc * c.n_pol * 16 + 2 * d_bytes + c.n_pol * p.N * 8 * 6 + p.N * 8
+        total += step * steps
+    ach = total / t_batch / 1e9
+    return {"kernel": "all step kernels of the 48 members (aggregate)", "bound": "hbm",
+            "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "algorithmic_bytes": int(total)}
+
+
+def batch_cpu_baseline(cfgs, bss, steps, sample_steps=2):
+    """The oracle on a bounded sample of the batch: one member of each grid and band
+    shape runs `sample_steps` Haydock steps (after its untimed setup); the batch's
+    oracle time is estimated as every member's steps at its shape's measured rate."""
+    import oracle as O
+
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    per_step = {}
+    for c, bs in zip(cfgs, bss):
+        key = (c.n_coarse, c.n_div, c.nc)
+        if key in per_step:
+            continue
+        Dv, Dc = O.overlaps(bs.vecs_coarse, bs.vecs_dense, c.n_coarse, c.n_div, c.nv, c.nc)
+        Kc = O.coarse_kernel(bs.vecs_coarse, bs.tau, c.nv, c.nc, c.n_coarse, c.n_div, c)
+        delta = O.transition_energies(bs.eps_dense, c.nv, c.nc)
+        op = O.InterpOperator(Dv, Dc, O.trilinear_weights(c.n_div), Kc, delta, c.n_coarse, c.n_div, c.nv, c.nc)
+        t0 = time.perf_counter()
+        O.haydock(op.apply, bs.P_flat(), sample_steps)
+        per_step[key] = (time.perf_counter() - t0) / sample_steps
+    t_total = sum(per_step[(c.n_coarse, c.n_div, c.nc)] * steps for c in cfgs)
+    n_chain_steps = sum(c.n_pol for c in cfgs) * steps
+    return {"value": round(n_chain_steps / t_total, 2), "unit": "chain-steps/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": (f"{sample_steps} Haydock steps (3 polarisations) of one member per shape "
+                       f"({len(per_step)} shapes) with the FP64 NumPy oracle after its untimed setup; "
+                       f"the batch's {len(cfgs)} members x {steps} steps estimated at those rates")}
 
 
 def spectrum_race(args):
