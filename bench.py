@@ -253,8 +253,10 @@ def main():
                            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                            "traffic_unit": "bytes per launch (not measured for this kernel)"}
         out["coarse_product_roofline_frac"] = round(achieved_gbs / HBM_PEAK_GBS, 4)
-    if not args.no_cpu_baseline and m3 is None:
+    if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, bs, args.cpu_steps)
+        if m3 is not None:
+            out["cpu_baseline"] = m3_cpu_baseline(cfg, args.m3, out["cpu_baseline"])
     prob.close()
     print(json.dumps(out), flush=True)
 
@@ -360,6 +362,29 @@ def batch_roofline(cfgs, probs, steps, t_batch):
     return {"kernel": "all step kernels of the 48 members (aggregate)", "bound": "hbm",
             "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "algorithmic_bytes": int(total)}
+
+
+def m3_cpu_baseline(cfg, w, m1, n_sample=256):
+    """The oracle's Method 3 step: its Method 1 step (measured above) plus the band
+    product, timed on a bounded sample (n_sample dense points x every offset, blocks of
+    the band's shape) and scaled to all dense points."""
+    import numpy as np
+
+    import oracle as O
+
+    off = O.m3.band_offsets(cfg.n_div, w)
+    npair = cfg.nv * cfg.nc
+    rng = np.random.default_rng(0)
+    blocks = rng.normal(size=(n_sample, len(off), npair, npair)) + 0j
+    x = rng.normal(size=(cfg.n_pol, cfg.n_trans)) + 0j
+    ks = np.arange(n_sample)
+    t0 = time.perf_counter()
+    O.m3.band_product(blocks, off, x, cfg.n_coarse, cfg.n_div, ks)
+    t_band = (time.perf_counter() - t0) * cfg.nk_dense / n_sample
+    t_step = 1.0 / m1["value"] + t_band
+    return {"value": round(1.0 / t_step, 4), "unit": "steps/s", "cores": m1["cores"], "kind": "oracle",
+            "sample": (m1["sample"] + f"; plus the band product of {len(off)} offsets timed on {n_sample} of the "
+                       f"{cfg.nk_dense} dense points and scaled ({t_band:.1f} s per step); the band build is setup")}
 
 
 def batch_cpu_baseline(cfgs, bss, steps, sample_steps=2):

@@ -141,11 +141,21 @@ def band_blocks(op, a_c: np.ndarray, S_c: np.ndarray, offsets: np.ndarray, s_d: 
     return out
 
 
+def band_product(blocks: np.ndarray, offsets: np.ndarray, x: np.ndarray, n_c: int, n_div: int,
+                 ks=None) -> np.ndarray:
+    """y_k = sum_o Delta(k, k + o) x_{k+o} for the dense points ks (all by default);
+    blocks [len(ks), n_off, npair, npair], x [n_rhs, N] -> y [n_rhs, len(ks), npair]."""
+    x = np.atleast_2d(x)
+    npair = blocks.shape[-1]
+    nk = n_c ** 3 * n_div ** 3
+    ks = np.arange(nk) if ks is None else np.asarray(ks)
+    nbr = band_neighbours(n_c, n_div, offsets)[ks]
+    xb = x.reshape(x.shape[0], nk, npair)
+    return np.einsum("kopq,rkoq->rkp", blocks, xb[:, nbr, :])
+
+
 def apply(op, blocks: np.ndarray, offsets: np.ndarray, x: np.ndarray) -> np.ndarray:
     """H^{M3} x = H^i x + sum_o Delta(k, k + o) x_{k+o} (blocks for every dense k)."""
     x = np.atleast_2d(x)
-    npair = op.nv * op.nc
-    nbr = band_neighbours(op.n_c, op.n_div, offsets)
-    xb = x.reshape(x.shape[0], op.nk, npair)
-    y = np.einsum("kopq,rkoq->rkp", blocks, xb[:, nbr, :])
+    y = band_product(blocks, offsets, x, op.n_c, op.n_div)
     return op.apply(x) + y.reshape(x.shape[0], -1)
