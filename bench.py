@@ -27,6 +27,27 @@ COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "hbm_counters_c1_f32.md")
 GEMV_SOURCE = os.path.join(ROOT, "paper_1602_01863_amd", "csrc", "gemv.hip")
 
 
+M3_SUMMARY = os.path.join(ROOT, "profiles", "m3_band_c1_f32.md")
+M3_SOURCE = os.path.join(ROOT, "paper_1602_01863_amd", "csrc", "m3.hip")
+
+
+def measured_m3_traffic(workload: str, dtype: str, w: float):
+    """HBM bytes per band-product launch from the committed counter summary (C1, FP32,
+    w = 1), or None if it does not cover this run or the kernel source has changed."""
+    import hashlib
+    import re
+
+    if workload != "c1" or dtype != "f32" or w != 1.0 or not os.path.exists(M3_SUMMARY):
+        return None
+    text = open(M3_SUMMARY).read()
+    m_t = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    m_h = re.search(r"m3_source_sha256_16:\s*([0-9a-f]+)", text)
+    if not (m_t and m_h):
+        return None
+    digest = hashlib.sha256(open(M3_SOURCE, "rb").read()).hexdigest()[:16]
+    return int(m_t.group(1)) if digest == m_h.group(1) else None
+
+
 def measured_traffic(workload: str, dtype: str):
     """HBM bytes per coarse-product launch from the committed rocprofv3 counter
     summary, or None if it does not cover this workload or the kernel source has
@@ -250,8 +271,9 @@ def main():
         ach = m3["band_product_GBps"]
         out["roofline"] = {"kernel": "Method 3 band product y = Delta x (k_m3_apply)", "bound": "hbm",
                            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                           "traffic_unit": "bytes per launch (not measured for this kernel)"}
+                           "frac": round(ach / HBM_PEAK_GBS, 4),
+                           "traffic": measured_m3_traffic(args.config, dtype, args.m3),
+                           "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"}
         out["coarse_product_roofline_frac"] = round(achieved_gbs / HBM_PEAK_GBS, 4)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, bs, args.cpu_steps)
