@@ -133,6 +133,32 @@ def test_matvec_independent_of_product_splits(bse, splits):
     prob.close()
 
 
+# the coarse product's other code paths: a column split longer than one LDS stage of
+# qbar (2048 / n_rhs entries) stages qbar in pieces; an odd N_c in FP32 storage leaves the
+# rows of K_c off 16-byte alignment, so every load is an element load
+ODD_NC = ti.tiny_config(n_coarse=5, n_div=2, nv=3, nc=3, n_orb=7, seed=15, n_pol=4)  # N_c = 1125
+PATH_CASES = [(ODD_NC, "f32"), (ODD_NC, "f64"), (ti.get_config("c0").with_(n_pol=4), "f32")]
+
+
+@pytest.mark.parametrize("cfg,dtype", PATH_CASES, ids=[f"{c.name}-{d}" for c, d in PATH_CASES])
+@pytest.mark.parametrize("splits", [1, 2, 0])
+@pytest.mark.parametrize("n_rhs", [3, 4])
+def test_matvec_product_paths_match_oracle(bse, cfg, dtype, splits, n_rhs):
+    op = oracle_operator(cfg)
+    prob = _problem(bse, cfg, dtype)
+    bse.bse_plan_set_gemv_splits(prob.plan, splits)
+    x = ti.random_vectors(op.N, n_rhs, 108)
+    xs = prob.vector(x)
+    y = prob.matvec(xs).cpu().numpy().astype(complex)
+    ref = op.apply(xs.cpu().numpy().astype(complex))
+    if dtype == "f64":
+        assert rel_l2(y, ref) < 1e-13
+    else:
+        assert np.all(np.abs(y - ref) <= product_bound(op, x, U32))
+        assert rel_l2(y, ref) < 2e-6
+    prob.close()
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_restrict_group_gives_same_matvec(bse, dtype):
     # one block per right-hand side, or one block for all three: same arithmetic per
