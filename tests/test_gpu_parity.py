@@ -159,6 +159,37 @@ def test_matvec_product_paths_match_oracle(bse, cfg, dtype, splits, n_rhs):
     prob.close()
 
 
+# 216 subpoints per cell with FP64 vectors: a cell's vector slice no longer fits the
+# restrict's LDS tiles, and the restrict falls back to reading the overlaps in their
+# input layout (k_restrict2); the prolong runs its one-block-per-cell form
+WIDE_CELL = ti.tiny_config(n_coarse=2, n_div=6, nv=3, nc=6, n_orb=9, seed=16, n_pol=3, steps=20)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32v64"])
+def test_wide_cell_matvec_and_chain_match_oracle(bse, dtype):
+    cfg = WIDE_CELL
+    op = oracle_operator(cfg)
+    prob = _problem(bse, cfg, dtype)
+    x = ti.random_vectors(op.N, 3, 109)
+    xs = prob.vector(x)
+    y = prob.matvec(xs).cpu().numpy().astype(complex)
+    ref = op.apply(xs.cpu().numpy().astype(complex))
+    if dtype == "f64":
+        assert rel_l2(y, ref) < 1e-13
+    else:
+        assert np.all(np.abs(y - ref) <= product_bound(op, x, U32))
+    # chain start and update forms of the same restrict: the head of the chain
+    P = bands(cfg).P_flat()
+    och = O.haydock(op.apply, P, cfg.steps)
+    ch = prob.haydock(P, cfg.steps)
+    a, b = ch["a"].cpu().numpy(), ch["b"].cpu().numpy()
+    tol = 1e-10 if dtype == "f64" else 1e-5
+    assert np.all(ch["status"].cpu().numpy() == bse.BSE_OK)
+    assert rel_l2(a[:, :10], och["a"][:, :10]) < tol
+    assert rel_l2(b[:, 1:11], och["b"][:, 1:11]) < tol
+    prob.close()
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_restrict_group_gives_same_matvec(bse, dtype):
     # one block per right-hand side, or one block for all three: same arithmetic per
