@@ -151,7 +151,7 @@ __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, V2, NV,
     using Rw = typename U::t;
     constexpr int PFU = (NE * kWave / U::P + NT - 1) / NT;  // staged 16-byte units per thread (n_div^3 <= 64)
     extern __shared__ double2 lds2[];
-    __shared__ double red[NR][2][2];
+    __shared__ double red[NR][NT / kWave][2];
     __shared__ double ftab[8 * kWave];
     const int ndiv3 = n_div * n_div * n_div;
     const int blk = NE * ndiv3;                // entries of one (cell, corner) block
@@ -264,82 +264,105 @@ __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, V2, NV,
         }
     }
 
-    // w = delta psi_i + C^H r [- b_i psi_{i-1}], with psi_i = s_i u_i in a chain
-    double s_cur = 1.0, c_prev = 0.0;
-    if (MODE == PROLONG_LANCZOS && rhs < NR) {
-        s_cur = chain[rhs].s_cur;                         // psi_i = s_i u_i
-        c_prev = chain[rhs].b_cur * chain[rhs].s_prev;    // b_i psi_{i-1} = b_i s_{i-1} u_{i-1}
-    }
-    double pw = 0.0, ww = 0.0;
-    if (active) {
-        const int64_t kd = (int64_t)cell * ndiv3 + lane;
-        const int64_t t0 = (int64_t)rhs * N + kd * NP;
-        // all loads of the lane first (psi_{i-1} unconditionally: before the second
-        // step its buffer holds no vector, and the select below drops it)
-        V2 xr[NV][NCH], pr[NV][NCH];
-        double dr[NV][NCH];
-        double2 yr[NV][NCH];
+    // w = delta psi_i + C^H r [- b_i psi_{i-1}] [+ s_i y], psi_i = s_i u_i in a chain,
+    // element by element: the lanes' C^H r pass through LDS (the staging buffers are
+    // free after the corner loop), one right-hand side at a time, so that the vector
+    // slices of the cell are read and written in contiguous runs and no lane holds
+    // its nine vector entries of every kind at once.
+    double2* accs = reinterpret_cast<double2*>(lds2);   // fits: 2 (nv^2 + nc^2) >= nv nc
+    const int nelem = ndiv3 * NP;
+    const int64_t cbase = (int64_t)cell * nelem;
+    double pwr[NR], wwr[NR];
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+    for (int r = 0; r < NR; ++r) pwr[r] = wwr[r] = 0.0;
 #pragma unroll
-            for (int q = 0; q < NCH; ++q) {
-                const int p = v * NC + min(h * NCH + q, NC - 1);
-                xr[v][q] = x[t0 + p];
-                dr[v][q] = delta[kd * NP + p];
-                if (MODE == PROLONG_LANCZOS) pr[v][q] = out[t0 + p];
-            }
-        if (yb) {   // Method 3 band product of u_i (uniform branch)
+    for (int r = 0; r < NR; ++r) {
+        __syncthreads();   // earlier readers of the buffers are done
+        if (active && rhs == r) {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int q = 0; q < NCH; ++q) yr[v][q] = yb[t0 + v * NC + min(h * NCH + q, NC - 1)];
+                for (int q = 0; q < NCH; ++q) {
+                    const int c = h * NCH + q;
+                    if (c < NC) accs[lane * NP + v * NC + c] = make_double2(acc[v][q].re, acc[v][q].im);
+                }
         }
-        __builtin_amdgcn_sched_barrier(0);
+        __syncthreads();
+        double s_cur = 1.0, c_prev = 0.0;
+        if (MODE == PROLONG_LANCZOS) {
+            s_cur = chain[r].s_cur;                       // psi_i = s_i u_i
+            c_prev = chain[r].b_cur * chain[r].s_prev;    // b_i psi_{i-1} = b_i s_{i-1} u_{i-1}
+        }
+        const int64_t rbase = (int64_t)r * N + cbase;
+        constexpr int EPT = 4;
+        for (int e0 = 0; e0 < nelem; e0 += EPT * NT) {
+            // all loads of the batch first, clamped (psi_{i-1} unconditionally: before
+            // the second step its buffer holds no vector, and the select below drops it)
+            V2 xr[EPT], pr[EPT];
+            double dr[EPT];
+            double2 yr[EPT];
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+            for (int u = 0; u < EPT; ++u) {
+                const int e = min(e0 + t + u * NT, nelem - 1);
+                xr[u] = x[rbase + e];
+                dr[u] = delta[cbase + e];
+                if (MODE == PROLONG_LANCZOS) pr[u] = out[rbase + e];
+            }
+            if (yb) {   // Method 3 band product of u_i (uniform branch)
 #pragma unroll
-            for (int q = 0; q < NCH; ++q) {
-                const int c = h * NCH + q;
-                if (c >= NC) continue;
-                const int p = v * NC + c;
-                const cd xv = cv(xr[v][q]);
-                const double dl = dr[v][q] * s_cur;
-                cd w = acc[v][q];
+                for (int u = 0; u < EPT; ++u) yr[u] = yb[rbase + min(e0 + t + u * NT, nelem - 1)];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                const int e = e0 + t + u * NT;
+                if (e >= nelem) break;
+                const cd xv = cv(xr[u]);
+                const double dl = dr[u] * s_cur;
+                const double2 a = accs[e];
+                cd w = cmake(a.x, a.y);
                 w.re = fma(dl, xv.re, w.re);
                 w.im = fma(dl, xv.im, w.im);
                 if (MODE == PROLONG_LANCZOS) {
-                    const cd pv = cv(pr[v][q]);
+                    const cd pv = cv(pr[u]);
                     const double pre = c_prev != 0.0 ? pv.re : 0.0;
                     const double pim = c_prev != 0.0 ? pv.im : 0.0;
                     w.re = fma(-c_prev, pre, w.re);
                     w.im = fma(-c_prev, pim, w.im);
                 }
                 if (yb) {
-                    w.re = fma(s_cur, yr[v][q].x, w.re);
-                    w.im = fma(s_cur, yr[v][q].y, w.im);
+                    w.re = fma(s_cur, yr[u].x, w.re);
+                    w.im = fma(s_cur, yr[u].y, w.im);
                 }
-                st(out + t0 + p, w);
+                st(out + rbase + e, w);
                 if (MODE == PROLONG_LANCZOS) {
                     const cd wr = rounded(w, out);
-                    pw = fma(xv.re, wr.re, pw);
-                    pw = fma(xv.im, wr.im, pw);
-                    ww = fma(wr.re, wr.re, ww);
-                    ww = fma(wr.im, wr.im, ww);
+                    pwr[r] = fma(xv.re, wr.re, pwr[r]);
+                    pwr[r] = fma(xv.im, wr.im, pwr[r]);
+                    wwr[r] = fma(wr.re, wr.re, wwr[r]);
+                    wwr[r] = fma(wr.im, wr.im, wwr[r]);
                 }
             }
+        }
     }
     if (MODE != PROLONG_LANCZOS) return;
 
-    pw = wave_sum(pw);
-    ww = wave_sum(ww);
-    if (lane == 0 && rhs < NR) {
-        red[rhs][h][0] = pw;
-        red[rhs][h][1] = ww;
+    // per right-hand side: lanes, then wavefronts in a fixed order
+    constexpr int NWV = NT / kWave;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const double pw = wave_sum(pwr[r]), ww = wave_sum(wwr[r]);
+        if (lane == 0) {
+            red[r][wave][0] = pw;
+            red[r][wave][1] = ww;
+        }
     }
     __syncthreads();
-    if (t < 2 * NR) {   // both halves of a right-hand side, fixed order
+    if (t < 2 * NR) {
         const int r = t >> 1, comp = t & 1;
-        ppart[((int64_t)cell * NR + r) * 2 + comp] = red[r][0][comp] + red[r][1][comp];
+        double sum = 0.0;
+        for (int w = 0; w < NWV; ++w) sum += red[r][w][comp];
+        ppart[((int64_t)cell * NR + r) * 2 + comp] = sum;
     }
 }
 
@@ -378,7 +401,8 @@ hipError_t prolong_launch(const Plan& p, int mode, const void* x, void* out, int
     const size_t lds = prolong3_lds(NE, g.ndiv3, NP, n_rhs, sizeof(M2));
     // staged form: whole 16-byte units per (cell, corner) block and an aligned base
     const bool units = ((size_t)NE * g.ndiv3 * sizeof(M2)) % 16 == 0 && ((uintptr_t)p.d & 15) == 0;
-    const size_t static_lds = 8 * kWave * sizeof(double) + kMaxRhs * 4 * sizeof(double);  // prefactors, partials
+    // prefactor table, per-wavefront chain partials (at most 2 kMaxRhs wavefronts)
+    const size_t static_lds = 8 * kWave * sizeof(double) + kMaxRhs * (2 * kMaxRhs) * 2 * sizeof(double);
     if (g.ndiv3 <= kWave && lds + static_lds <= lds_limit() && units) {
         switch (n_rhs) {
             case 1: prolong3_go<M2, V2, NV, NC, 1>(p, mode, xv, ov, cs, lds, s); break;
