@@ -12,7 +12,9 @@
 // in flight while corner z is computed), so every wavefront of the cell reads them
 // from LDS; the 8 coarse blocks r_{k~z} sit in LDS as well.  Two wavefronts per
 // right-hand side split the conduction index c in halves, which halves the FP64
-// accumulators each lane holds.
+// accumulators each lane holds.  After the corner loop the lanes' sums pass through
+// LDS, and the whole block applies the diagonal and the chain terms element by element
+// over the cell's contiguous slice of each vector.
 
 #include <hip/hip_runtime.h>
 
