@@ -18,7 +18,7 @@ import oracle as O
 import tbinputs as ti
 
 from _cases import bands, rel_l2
-from _gpu import U32, gpu_overlaps_to_oracle
+from _gpu import U32, U64, gpu_overlaps_to_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -80,11 +80,13 @@ def test_c1_coarse_kernel_rows(c1):
     assert torch.equal(Kfull, Kfull.conj().transpose(0, 1).contiguous())
 
 
-def test_c1_matvec_sampled_cells(c1, c1_oracle_pieces):
-    bs, prob = c1
-    Dv, Dc, delta = c1_oracle_pieces
+def _sampled_cells(bs, prob, pieces, seed, unit, factors, rel):
+    """Matvec outputs of SAMPLE_CELLS against the oracle, computed one by one: the K_c
+    rows of the cells' corners and the restriction of the whole vector; componentwise
+    within `factors` units `unit` of the sum of |terms|, and in relative L2."""
+    Dv, Dc, delta = pieces
     f = O.trilinear_weights(CFG.n_div)
-    x = prob.vector(ti.random_vectors(CFG.n_trans, 3, 201))
+    x = prob.vector(ti.random_vectors(CFG.n_trans, 3, seed))
     y = prob.matvec(x).cpu().numpy().astype(complex)
     xh = x.cpu().numpy().astype(complex)
     nbr = O.neighbour_table(CFG.n_coarse)
@@ -102,12 +104,44 @@ def test_c1_matvec_sampled_cells(c1, c1_oracle_pieces):
         r[:, k * np_:(k + 1) * np_] = (rows[i] @ qbar.T).T
         rabs[:, k * np_:(k + 1) * np_] = (np.abs(rows[i]) @ np.abs(qabs).T).T
     ref = delta[None] * xh + op.prolong(r)
-    bound = 10 * U32 * np.abs(np.abs(delta)[None] * np.abs(xh) + aop.prolong(rabs))
+    bound = factors * unit * np.abs(np.abs(delta)[None] * np.abs(xh) + aop.prolong(rabs))
     ndiv3 = CFG.n_div3
     for cell in SAMPLE_CELLS:
         sl = slice(cell * ndiv3 * np_, (cell + 1) * ndiv3 * np_)
         assert np.all(np.abs(y[:, sl] - ref[:, sl]) <= bound[:, sl]), f"cell {cell}"
-        assert rel_l2(y[:, sl], ref[:, sl]) < 2e-6
+        assert rel_l2(y[:, sl], ref[:, sl]) < rel
+
+
+def test_c1_matvec_sampled_cells(c1, c1_oracle_pieces):
+    bs, prob = c1
+    _sampled_cells(bs, prob, c1_oracle_pieces, 201, U32, 10, 2e-6)
+
+
+def test_c1_fp64_matvec_sampled_cells_and_chain_head(bse, c1_oracle_pieces):
+    """The all-FP64 form at full size: sampled matvec cells within 4096 FP64 units of
+    the sum of |terms| (the library's K_c lattice sums and the oracle's are summed in
+    different orders over up to 2 000 plane waves), and
+    the chains against the oracle's FP64 chains: the head to 1e-9 and eps2 at the
+    converged broadenings (0.2, 0.3 eV) to 1e-7 (the FP32-storage forms are held to
+    1e-6 there)."""
+    bs = bands(CFG)
+    prob = bse.problem_from_bands(bs, CFG, dtype="f64", max_rhs=3)
+    _sampled_cells(bs, prob, c1_oracle_pieces, 204, U64, 4096, 1e-12)
+    ch = prob.haydock(bs.P_flat(), CFG.steps)
+    ref = _read_chains("c1_oracle_chain.txt")
+    a, b = ch["a"].cpu().numpy(), ch["b"].cpu().numpy()
+    assert np.all(ch["status"].cpu().numpy() == bse.BSE_OK)
+    np.testing.assert_allclose(ch["pnorm2"].cpu().numpy(), ref["pnorm2"], rtol=1e-12)
+    for r in range(3):
+        assert rel_l2(a[r, :12], ref["a"][r, :12]) < 1e-9
+        assert rel_l2(b[r, 1:13], ref["b"][r, 1:13]) < 1e-9
+    om, pref = CFG.omega(), CFG.prefactor()
+    for eta in (0.2, 0.3):
+        eps = prob.continued_fraction(ch, pref, om, eta).cpu().numpy()
+        oeps = O.continued_fraction(ref["a"], ref["b"], ref["pnorm2"], pref, om, eta)
+        for r in range(3):
+            assert rel_l2(eps[r].imag, oeps[r].imag) < 1e-7, (eta, r)
+    prob.close()
 
 
 def test_c1_operator_hermitian_at_full_size(c1):
