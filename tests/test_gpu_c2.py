@@ -1,9 +1,10 @@
-"""Full-size parity of the precision form on its workload (10^3 coarse x 4 divisions,
+"""Full-size parity on the precision form's workload (10^3 coarse x 4 divisions,
 4v6c: N = 1 536 000, K_c 24 000^2 block-scaled BF16), in the launch configuration
 the benchmark times: sampled cells of the matvec against the FP64 oracle, computed
 one by one (the K_c rows of the cells' corners and the restriction of the whole
 vector), within the format's componentwise bound; adjointness of the applied
-operator at full size."""
+operator at full size.  The same cells in FP32 storage, where the coarse product
+stages qbar in pieces."""
 
 from __future__ import annotations
 
@@ -80,6 +81,42 @@ def test_c2_bf16_matvec_sampled_cells(c2):
         # the kernel part carries the format's rounding: well below one BF16 unit overall
         kd, kr = y[:, sl] - delta[None, sl] * xh[:, sl], ref[:, sl] - delta[None, sl] * xh[:, sl]
         assert rel_l2(kd, kr) < 2 * U_BF16
+
+
+def test_c2_fp32_matvec_sampled_cells(bse):
+    """FP32 storage at C2 (the coarse product stages qbar in pieces at this size): the
+    same sampled cells within 10 FP32 units of the sum of |terms|."""
+    bs = bands(CFG)
+    prob = bse.problem_from_bands(bs, CFG, dtype="f32", max_rhs=3)
+    Dv, Dc = O.overlaps(bs.vecs_coarse, bs.vecs_dense, CFG.n_coarse, CFG.n_div, CFG.nv, CFG.nc)
+    delta = O.transition_energies(bs.eps_dense, CFG.nv, CFG.nc)
+    f = O.trilinear_weights(CFG.n_div)
+    x = ti.random_vectors(CFG.n_trans, 3, 404)
+    xs = prob.vector(x)
+    y = prob.matvec(xs).cpu().numpy().astype(complex)
+    xh = xs.cpu().numpy().astype(complex)
+    nbr = O.neighbour_table(CFG.n_coarse)
+    need = np.unique(nbr[SAMPLE_CELLS].ravel())
+    rows = O.coarse_kernel_block_rows(bs.vecs_coarse, bs.tau, CFG.nv, CFG.nc, CFG.n_coarse, CFG.n_div, CFG, need)
+    np_ = CFG.n_pair
+    op = O.InterpOperator(Dv, Dc, f, None, delta, CFG.n_coarse, CFG.n_div, CFG.nv, CFG.nc)
+    aop = O.InterpOperator(np.abs(Dv).astype(complex), np.abs(Dc).astype(complex), f, None, np.abs(delta),
+                           CFG.n_coarse, CFG.n_div, CFG.nv, CFG.nc)
+    qbar = op.restrict(xh)
+    qabs = aop.restrict(np.abs(xh))
+    r = np.zeros((3, CFG.n_trans_coarse), dtype=complex)
+    rabs = np.zeros((3, CFG.n_trans_coarse), dtype=complex)
+    for i, k in enumerate(need):
+        r[:, k * np_:(k + 1) * np_] = (rows[i] @ qbar.T).T
+        rabs[:, k * np_:(k + 1) * np_] = (np.abs(rows[i]) @ np.abs(qabs).T).T
+    ref = delta[None] * xh + op.prolong(r)
+    bound = 10 * U32 * np.abs(np.abs(delta)[None] * np.abs(xh) + aop.prolong(rabs))
+    ndiv3 = CFG.n_div3
+    for cell in SAMPLE_CELLS:
+        sl = slice(cell * ndiv3 * np_, (cell + 1) * ndiv3 * np_)
+        assert np.all(np.abs(y[:, sl] - ref[:, sl]) <= bound[:, sl]), f"cell {cell}"
+        assert rel_l2(y[:, sl], ref[:, sl]) < 2e-6
+    prob.close()
 
 
 def test_c2_bf16_operator_adjoint_at_full_size(c2):
