@@ -162,3 +162,72 @@ def test_c0_chain_is_stable_and_spectrum_positive():
     eps = O.continued_fraction(ch["a"], ch["b"], ch["pnorm2"], cfg.prefactor(), cfg.omega(),
                                cfg.eta)
     assert np.all(eps.imag > 0)
+
+
+# ---- where a plain chain stops being fixed by its inputs (Eqs. ai-ci, no reorthogonalisation) ----
+def _first_above(x, ref, tol):
+    """Index of the first entry with |x - ref| > tol |ref| (len(ref) if none)."""
+    bad = np.abs(np.asarray(x) - ref) > tol * np.abs(ref)
+    return int(np.argmax(bad)) if bad.any() else len(ref)
+
+
+def test_chain_window_c0_one_ulp_perturbation():
+    """The C0 chain (FP64, 200 steps) against itself with the diagonal of Eq. (bse1)
+    moved by one unit in the last place.  Without reorthogonalisation, rounding decides
+    when converged states re-enter the chain, and a perturbation of 1e-16 grows by about
+    17x per step once the first state has converged: the coefficients agree to 1e-10
+    through the first 20 (the window the GPU chain tests hold to 1e-10) and differ by
+    more than 1e-2 before the 50th, so no precision reproduces 50 of them.  eps2 at the
+    workload's eta = 0.1 eV moves by ~3e-5; at 0.3 eV by ~1e-12."""
+    cfg = ti.get_config("c0")
+    op = oracle_operator(cfg)
+    P = bands(cfg).P_flat()
+    c1 = O.haydock(op.apply, P, cfg.steps)
+    op2 = oracle_operator(cfg)
+    op2.delta = np.nextafter(op.delta, np.inf)
+    c2 = O.haydock(op2.apply, P, cfg.steps)
+    first_a = _first_above(c2["a"][0], c1["a"][0], 1e-10)
+    first_b = _first_above(c2["b"][0, 1:], c1["b"][0, 1:], 1e-10)
+    assert min(first_a, first_b) >= 20
+    assert np.max(np.abs(c2["a"][0, 20:50] - c1["a"][0, 20:50]) / np.abs(c1["a"][0, 20:50])) > 1e-2
+    om = cfg.omega()
+    sens = {}
+    for eta in (0.1, 0.3):
+        e1 = O.continued_fraction(c1["a"], c1["b"], c1["pnorm2"], cfg.prefactor(), om, eta)
+        e2 = O.continued_fraction(c2["a"], c2["b"], c2["pnorm2"], cfg.prefactor(), om, eta)
+        sens[eta] = rel_l2(e2.imag, e1.imag)
+    assert 1e-6 < sens[0.1] < 1e-4
+    assert sens[0.3] < 1e-10
+
+
+def _golden_c1(name):
+    import os
+    rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", name))
+    m = ti.get_config("c1").steps
+    return dict(pnorm2=rows[:, 1], a=rows[:, 3:3 + m], b=rows[:, 3 + m:4 + 2 * m])
+
+
+def test_chain_window_c1_fp32_storage():
+    """The C1 chains of the oracle in FP64 and with every stored vector rounded to
+    complex64 (the golden files written by tests/golden/make_oracle_chains.py):
+    they agree to 1e-6 over the first 12 a_n and b_{n+1} of every polarisation (the
+    window the GPU FP32 chain tests hold to 1e-6), and differ by more than 1e-2
+    before the 25th, so 50 coefficients are out of reach of FP32 storage.  eps2 at
+    the workload's eta = 0.05 eV differs by ~1.2e-2 .. 1.5e-2 (the 300-step chain has
+    not converged there), at 0.1 eV by ~1.5e-4, and at 0.2 eV and above by < 1e-7."""
+    cfg = ti.get_config("c1")
+    ref = _golden_c1("c1_oracle_chain.txt")
+    emu = _golden_c1("c1_oracle_chain_f32emu.txt")
+    om = cfg.omega()
+    for r in range(3):
+        assert _first_above(emu["a"][r], ref["a"][r], 1e-6) >= 12
+        assert _first_above(emu["b"][r, 1:], ref["b"][r, 1:], 1e-6) >= 12
+        assert np.max(np.abs(emu["a"][r, 12:25] - ref["a"][r, 12:25]) / np.abs(ref["a"][r, 12:25])) > 1e-2
+    err = {}
+    for eta in (0.05, 0.1, 0.2, 0.3):
+        e1 = O.continued_fraction(ref["a"], ref["b"], ref["pnorm2"], cfg.prefactor(), om, eta)
+        e2 = O.continued_fraction(emu["a"], emu["b"], emu["pnorm2"], cfg.prefactor(), om, eta)
+        err[eta] = max(rel_l2(e2[r].imag, e1[r].imag) for r in range(3))
+    assert 5e-3 < err[0.05] < 3e-2
+    assert 5e-5 < err[0.1] < 5e-4
+    assert err[0.2] < 1e-7 and err[0.3] < 1e-7

@@ -144,3 +144,69 @@ def test_kernel_gauge_covariance():
     # pair (v, c, k): u*_v u_c picks up conj(t_v) t_c
     u = (np.conj(th[:, :2, None]) * th[:, None, 2:]).reshape(-1)
     np.testing.assert_allclose(K2, np.conj(u)[:, None] * K1 * u[None, :], atol=1e-15)
+
+
+# ---- closed-form pins of the kernel's scales (Eq. bse2, Eq. bse3a, Eq. bse3b / Wcoul) ----
+PI = np.pi
+
+
+def test_w_model_literal_values():
+    """W(Q) = 4 pi / (eps_inf |Q|^2 + lambda^2) with Cartesian |Q| = 2 pi |q + G| of the
+    cubic cell (lattice constant 1): literal values at eps_inf = 12, lambda = 0.3."""
+    eps, lam = 12.0, 0.3
+    cases = [((0.5, 0.0, 0.0), 4 * PI / (12 * PI ** 2 + 0.09)),          # |2 pi Q|^2 = pi^2
+             ((0.0, 0.0, 0.0), 4 * PI / 0.09),
+             ((1.0, 1.0, 0.0), 4 * PI / (96 * PI ** 2 + 0.09)),          # 8 pi^2
+             ((0.25, -0.5, 1.0), 4 * PI / (12 * 4 * PI ** 2 * 1.3125 + 0.09))]
+    for Q, expect in cases:
+        assert O.w_model(np.array(Q), eps, lam) == pytest.approx(expect, rel=1e-15)
+    got = O.w_model(np.array([c[0] for c in cases]), eps, lam)
+    np.testing.assert_allclose(got, [c[1] for c in cases], rtol=1e-15)
+
+
+def _two_site_hybrid(nk):
+    """One orbital on each of two sites, tau_A = 0 and tau_B = (1/4, 1/4, 1/4), and the
+    same bonding / antibonding pair at every k: v = (A + B)/sqrt 2, c = (A - B)/sqrt 2."""
+    s = 1.0 / np.sqrt(2.0)
+    vecs = np.empty((nk, 2, 2), dtype=np.complex128)
+    vecs[:, 0] = (s, s)
+    vecs[:, 1] = (s, -s)
+    tau = np.array([[0.0, 0.0, 0.0], [0.25, 0.25, 0.25]])
+    return vecs, tau
+
+
+def test_kernel_exchange_closed_form_two_sites():
+    """Exchange scale: with W switched off, K_c = (E_K / N_k) 2 X (Eq. bse2) and
+    X = sum_{G != 0} v(G) |M_cv(G)|^2 with v(G) = 4 pi / |2 pi G|^2 (Eq. bse3a).
+    For the hybridised pair M_cv(k,k;G) = (1 - exp(i 2 pi G.tau_B)) / 2, so
+    |M_cv|^2 = sin^2(pi (G1 + G2 + G3) / 4), the same for every (k, k').
+    Shell by shell over |G|^2 <= 4 (6, 12, 8 and 6 vectors):
+      |G|^2 = 1: 6 (1/pi) (1/2)    = 3/pi
+      |G|^2 = 2: 6 of 12 with s = +-2, each 1/(2 pi)  = 3/pi
+      |G|^2 = 3: 8 (1/(3 pi)) (1/2) = 4/(3 pi)
+      |G|^2 = 4: 6 (1/(4 pi)) 1     = 3/(2 pi)
+    X = 53/(6 pi), so every element is (E_K / N_k) 53/(3 pi).  A dropped factor 2,
+    a reduced |G| in v, or a wrong sign of the exchange fails this."""
+    cfg = ti.tiny_config(n_coarse=2, n_div=3, nv=1, nc=1, n_orb=2).with_(eps_inf=1e30, lam=1e15)
+    vecs, tau = _two_site_hybrid(cfg.nk_coarse)
+    K = O.coarse_kernel(vecs, tau, 1, 1, cfg.n_coarse, cfg.n_div, cfg)
+    expect = cfg.kernel_energy / cfg.nk_dense * 53.0 / (3.0 * PI)
+    np.testing.assert_allclose(K, np.full(K.shape, expect), rtol=1e-13, atol=0)
+
+
+def test_kernel_direct_closed_form_two_sites_q0():
+    """Direct scale and sign at q = 0 (Eq. bse3b with the model W): for the same pair,
+    M_cc(k,k;Q) conj(M_vv(k,k;Q)) = cos^2(pi (Q1 + Q2 + Q3) / 4), which is 1 at G = 0,
+    1/2 on |G|^2 = 1 and 3, 1 on the six |G|^2 = 2 vectors with G1 + G2 + G3 = 0 and 0
+    on the rest.  So on the diagonal blocks
+      D = <W>_0 + 3 W_1 + 6 W_2 + 4 W_3,  W_n = 4 pi / (12 (2 pi)^2 n + 0.09),
+    <W>_0 the mini-cell mean of W at q = 0, and K_c = (E_K / N_k) (2 X - D) with X of
+    the exchange pin.  W in reduced |Q| (12 n + 0.09) or +D fails this."""
+    cfg = ti.tiny_config(n_coarse=2, n_div=2, nv=1, nc=1, n_orb=2)
+    vecs, tau = _two_site_hybrid(cfg.nk_coarse)
+    K = O.coarse_kernel(vecs, tau, 1, 1, cfg.n_coarse, cfg.n_div, cfg)
+    Wn = [4 * PI / (12.0 * 4 * PI ** 2 * n + 0.09) for n in (1, 2, 3)]
+    w0 = O.w_q0_average(cfg.n_coarse, cfg.n_div, 12.0, 0.3, cfg.q0_quad)
+    D = w0 + 3 * Wn[0] + 6 * Wn[1] + 4 * Wn[2]
+    expect = cfg.kernel_energy / cfg.nk_dense * (2 * 53.0 / (6.0 * PI) - D)
+    np.testing.assert_allclose(np.diag(K), np.full(cfg.nk_coarse, expect), rtol=1e-13, atol=0)
