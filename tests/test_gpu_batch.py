@@ -6,9 +6,12 @@ from __future__ import annotations
 import numpy as np
 import pytest
 
+import oracle as O
 import tbinputs as ti
 
-from _cases import bands, rel_l2
+from _cases import bands, oracle_operator, oracle_parts, rel_l2
+from _gpu import U32
+from _sampled import check_sampled_cells, oracle_pieces
 
 pytestmark = pytest.mark.gpu
 
@@ -85,3 +88,114 @@ def test_autotune_picks_a_setting_and_keeps_results(bse, tmp_path):
     again = autotune(p, P, cache=cache)
     assert again["cached"] and (again["splits"], again["group"]) == (res["splits"], res["group"])
     p.close()
+
+
+def _window(ref, other, tol):
+    """Leading coefficients where `other` agrees with `ref` to tol (relative), min over chains."""
+    out = []
+    for key, lo in (("a", 0), ("b", 1)):
+        x, y = other[key][:, lo:], ref[key][:, lo:]
+        bad = np.abs(x - y) > tol * np.abs(y)
+        out += [int(np.argmax(row)) if row.any() else row.size for row in bad]
+    return min(out)
+
+
+def test_batch_chains_match_the_oracle(bse):
+    """Every member's batched chains (Eqs. ai-ci; 200 steps, the batching workload's
+    length) against the oracle's FP64 chains of the same Hamiltonian: the ±delta
+    displaced member, the FP32-vector and FP64-vector members and the BF16 member.
+
+    * head: the oracle against its own rounding-perturbed run (the FP64 member against
+      a one-ulp change of the diagonal, the FP32-storage members against complex64
+      storage of every vector) stays at the rounding floor and then departs, growing
+      17-50x per step, once converged states re-enter.  Two steps before it first
+      departs by more than the tolerance, the batched coefficients agree with the
+      oracle to 1e-10 (FP64) or 1e-6 (FP32); that window must hold at least 10
+      coefficients.  The BF16 member: a_1 within the
+      format bound 2^-8 <|qbar_1|, |K_c| |qbar_1|> (K_c entries rounded to 8 significant
+      bits, block scales are powers of two).
+    * eps2 at eta = 0.5 eV, where 200 steps have converged (the oracle's FP32-storage
+      emulation moves it by < 1e-7 there): 1e-10 (FP64), 1e-6 (FP32 storage), 1e-3
+      (BF16 coarse kernel)."""
+    steps = 200
+    probs = [bse.problem_from_bands(bands(c), c, dtype=dt, max_rhs=c.n_pol) for c, dt in MEMBERS]
+    Ps = [bands(c).P_flat() for c, _ in MEMBERS]
+    batch = bse.BSEBatch(probs, Ps, steps, n_branches=3)
+    chains = [_host(ch) for ch in batch.run()]
+    torch.cuda.synchronize()
+    om = np.linspace(0.0, 16.0, 800)
+    for (cfg, dt), got, P in zip(MEMBERS, chains, Ps):
+        assert np.all(got["status"] == bse.BSE_OK) and np.all(got["steps"] == steps), cfg.name
+        op = oracle_operator(cfg)
+        ref = O.haydock(op.apply, P, steps)
+        np.testing.assert_allclose(got["pnorm2"], ref["pnorm2"], rtol=1e-12)
+        if dt == "bf16":
+            bs, Dv, Dc, f, Kc, delta = oracle_parts(cfg)
+            psi = P / np.sqrt(ref["pnorm2"])[:, None]
+            aop = O.InterpOperator(np.abs(Dv).astype(complex), np.abs(Dc).astype(complex), f,
+                                   np.abs(Kc).astype(complex), delta, cfg.n_coarse, cfg.n_div, cfg.nv, cfg.nc)
+            qa = aop.restrict(np.abs(psi))
+            bound = 2.0 ** -8 * np.real(np.sum(np.abs(qa) * (np.abs(Kc) @ np.abs(qa).T).T, axis=1))
+            assert np.all(np.abs(got["a"][:, 0] - ref["a"][:, 0]) <= bound + 1e-12), cfg.name
+            tol_eps = 1e-3
+        else:
+            tol = 1e-10 if dt == "f64" else 1e-6
+            if dt == "f64":
+                op2 = oracle_operator(cfg)
+                op2.delta = np.nextafter(op.delta, np.inf)
+                pert = O.haydock(op2.apply, P, 40)
+            else:
+                pert = O.haydock(op.apply, P, 40, round_dtype=np.complex64)
+            head = dict(a=ref["a"][:, :40], b=ref["b"][:, :41])
+            w = _window(head, pert, tol) - 2
+            assert w >= 10, (cfg.name, w)
+            for r in range(P.shape[0]):
+                assert np.all(np.abs(got["a"][r, :w] - ref["a"][r, :w]) <= tol * np.abs(ref["a"][r, :w])), (cfg.name, r)
+                assert np.all(np.abs(got["b"][r, 1:w + 1] - ref["b"][r, 1:w + 1])
+                              <= tol * np.abs(ref["b"][r, 1:w + 1])), (cfg.name, r)
+            tol_eps = 1e-10 if dt == "f64" else 1e-6
+        eps = O.continued_fraction(got["a"], got["b"], got["pnorm2"], cfg.prefactor(), om, 0.5)
+        oeps = O.continued_fraction(ref["a"], ref["b"], ref["pnorm2"], cfg.prefactor(), om, 0.5)
+        for r in range(P.shape[0]):
+            assert rel_l2(eps[r].imag, oeps[r].imag) < tol_eps, (cfg.name, r)
+    batch.close()
+    for p in probs:
+        p.close()
+
+
+C3_SHAPES = [next(c for c in ti.batch_configs() if (c.n_coarse, c.n_div, c.nc) == shape)
+             for shape in ((6, 3, 3), (8, 4, 6))]
+
+
+@pytest.mark.parametrize("cfg", C3_SHAPES, ids=lambda c: c.name)
+def test_batch_workload_shapes_against_the_oracle(bse, cfg):
+    """The two larger grid shapes of the 48-member batching workload, one member each
+    (6^3 x 3 displaced by +delta with 3v3c; 8^3 x 4 displaced by -delta with 3v6c), in
+    FP32 storage as the workload runs them:
+    * sampled matvec cells against the oracle, within 10 FP32 units of the sum of
+      |terms| of each output and 2e-6 in relative L2;
+    * the member's chains run in a batch (200 steps, 3 polarisations) against the
+      oracle's FP64 chain head to 1e-6, up to two steps before the oracle's
+      complex64-storage emulation first departs from FP64 by more than 1e-6 (at
+      least 8 coefficients)."""
+    bs = bands(cfg)
+    prob = bse.problem_from_bands(bs, cfg, dtype="f32", max_rhs=3)
+    cells = np.array([0, cfg.nk_coarse // 3, cfg.nk_coarse - 1])
+    check_sampled_cells(cfg, bs, prob, oracle_pieces(cfg, bs), cells, 301, U32, 10, 2e-6)
+    P = bs.P_flat()
+    batch = bse.BSEBatch([prob], [P], 200, n_branches=1)
+    got = _host(batch.run()[0])
+    torch.cuda.synchronize()
+    assert np.all(got["status"] == bse.BSE_OK)
+    op = oracle_operator(cfg)
+    n = 16
+    ref = O.haydock(op.apply, P, n)
+    emu = O.haydock(op.apply, P, n, round_dtype=np.complex64)
+    w = _window(ref, emu, 1e-6) - 2
+    assert w >= 8, w
+    np.testing.assert_allclose(got["pnorm2"], ref["pnorm2"], rtol=1e-12)
+    for r in range(3):
+        assert np.all(np.abs(got["a"][r, :w] - ref["a"][r, :w]) <= 1e-6 * np.abs(ref["a"][r, :w])), r
+        assert np.all(np.abs(got["b"][r, 1:w + 1] - ref["b"][r, 1:w + 1]) <= 1e-6 * np.abs(ref["b"][r, 1:w + 1])), r
+    batch.close()
+    prob.close()
