@@ -23,7 +23,9 @@
  *
  * Memory: every pointer documented "device" must point to device memory of the
  * current HIP device; "host" pointers to host memory.  The library never
- * allocates device memory: scratch space is the caller's workspace.  All
+ * allocates device memory: scratch space is the caller's workspace (the one
+ * exception, bse_dense_backward_noalloc, uses a fixed array in the library's
+ * device code instead).  All
  * device work is enqueued on the given stream, in stream order, and the calls
  * return without waiting for it unless stated otherwise.
  *
@@ -279,6 +281,19 @@ bse_status bse_dense_forward(const float* x, const float* W, const float* b, flo
 bse_status bse_dense_backward(const float* x, const float* W, const float* z, const float* dy,
                               float* dx, float* dW, float* db, int32_t batch, int32_t n_in,
                               int32_t n_out, int32_t act, float* work, hipStream_t stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): the same backward pass as
+ * bse_dense_backward without the caller's `work` buffer.  dz lives in a scratch array
+ * the library holds in device memory, one per device, from the first call on that
+ * device until the process ends (4 MiB: batch * n_out <= 2^20 entries; larger calls
+ * return BSE_ERR_WORKSPACE before any launch).  The call allocates nothing.  Every call
+ * on one device shares that device's array: calls that overlap on one device (two
+ * streams, or two threads) race and must be ordered by the caller.  Results equal
+ * bse_dense_backward's bit for bit (same kernels, same order). */
+bse_status bse_dense_backward_noalloc(const float* x, const float* W, const float* z, const float* dy,
+                                      float* dx, float* dW, float* db, int32_t batch, int32_t n_in,
+                                      int32_t n_out, int32_t act, hipStream_t stream);
 
 /* Mean squared error over n entries: *loss = mean (y - t)^2 (FP64, fixed-order
  * sum, one device double) and dy = 2 (y - t) / n (skipped when dy is NULL). */

@@ -40,7 +40,7 @@ EXPORTED = [
     "bse_build_coarse_kernel", "bse_plan_create", "bse_plan_destroy", "bse_interp_matvec",
     "bse_haydock_run", "bse_continued_fraction", "bse_plan_set_timing", "bse_plan_get_timing",
     "bse_plan_set_gemv_splits", "bse_plan_set_restrict_group", "bse_batch_create", "bse_batch_launch",
-    "bse_batch_destroy", "bse_dense_forward", "bse_dense_backward", "bse_mse_loss", "bse_adam_step",
+    "bse_batch_destroy", "bse_dense_forward", "bse_dense_backward", "bse_dense_backward_noalloc", "bse_mse_loss", "bse_adam_step",
     "bse_to_bf16", "bse_dense_forward_bf16", "bse_continued_fraction_terminated",
     "bse_build_divergence_coefficient", "bse_m3_band_info", "bse_build_m3_band", "bse_plan_set_m3_band",
 ]
@@ -92,6 +92,7 @@ def _load():
         "bse_batch_destroy": (None, [vp]),
         "bse_dense_forward": (i32, [vp, vp, vp, vp, vp, i32, i32, i32, i32, vp]),
         "bse_dense_backward": (i32, [vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, vp, vp]),
+        "bse_dense_backward_noalloc": (i32, [vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, vp]),
         "bse_mse_loss": (i32, [vp, vp, vp, vp, i64, vp]),
         "bse_adam_step": (i32, [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, i32, vp]),
@@ -314,6 +315,12 @@ def bse_dense_backward(x, W, z, dy, dx, dW, db, batch, n_in, n_out, act, work, s
     _check(_lib.bse_dense_backward(_ptr(x), _ptr(W), _ptr(z), _ptr(dy), _ptr(dx), _ptr(dW), _ptr(db), int(batch),
                                    int(n_in), int(n_out), int(act), _ptr(work), _stream(stream)),
            "bse_dense_backward")
+
+
+def bse_dense_backward_noalloc(x, W, z, dy, dx, dW, db, batch, n_in, n_out, act, stream=None):
+    _check(_lib.bse_dense_backward_noalloc(_ptr(x), _ptr(W), _ptr(z), _ptr(dy), _ptr(dx), _ptr(dW), _ptr(db),
+                                           int(batch), int(n_in), int(n_out), int(act), _stream(stream)),
+           "bse_dense_backward_noalloc")
 
 
 def bse_mse_loss(y, t, dy, loss, n, stream=None):

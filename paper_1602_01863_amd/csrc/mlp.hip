@@ -11,6 +11,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 #include "bse_device.hpp"
 #include "bse_plan.hpp"
 
@@ -228,6 +230,58 @@ __global__ __launch_bounds__(256) void k_cf_terminated(const double* __restrict_
     eps_im[i] = c * ti / den;
 }
 
+// ---- scratch of bse_dense_backward_noalloc --------------------------------------------
+// dz = dy act'(z) of one call, in a file-scope device array instead of a caller buffer.
+// Every device that runs the library holds its own copy until the process ends.  In
+// host code the array's name is not a device address: host code uses only the address
+// hipGetSymbolAddress returns for the current device (kept per device below).
+constexpr int64_t kNoAllocMaxEntries = (int64_t)1 << 20;   // batch * n_out <= 2^20 (4 MiB)
+static __device__ __align__(256) float scratch[kNoAllocMaxEntries];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch_dev[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up once per device)
+static hipError_t scratch_address(float** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = static_cast<float*>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+// dz, dW, db and dx of the layer (see bse_dense_backward), dz in `work`
+static hipError_t enqueue_dense_backward(const float* x, const float* W, const float* z, const float* dy, float* dx,
+                                         float* dW, float* db, int batch, int n_in, int n_out, int act, float* work,
+                                         hipStream_t stream) {
+    const int64_t n = (int64_t)batch * n_out;
+    hipLaunchKernelGGL(k_act_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, z, dy, work, n, act);
+    // dW [n_out][n_in] = dz^T x ; db = column sums of dz ; dx [batch][n_in] = dz W
+    hipLaunchKernelGGL((k_gemm<true, false>), dim3((n_in + kTile - 1) / kTile, (n_out + kTile - 1) / kTile), dim3(256),
+                       0, stream, work, x, nullptr, nullptr, dW, n_out, n_in, batch, (int)BSE_ACT_NONE);
+    hipLaunchKernelGGL(k_colsum, dim3((n_out + 255) / 256), dim3(256), 0, stream, work, db, batch, n_out);
+    if (dx)
+        hipLaunchKernelGGL((k_gemm<false, false>), dim3((n_in + kTile - 1) / kTile, (batch + kTile - 1) / kTile),
+                           dim3(256), 0, stream, work, W, nullptr, nullptr, dx, batch, n_in, n_out, (int)BSE_ACT_NONE);
+    return hipGetLastError();
+}
+
+static bool dense_backward_args_ok(const float* x, const float* W, const float* z, const float* dy, const float* dW,
+                                   const float* db, int batch, int n_in, int n_out, int act) {
+    return x && W && dy && dW && db && !(act == BSE_ACT_GELU && !z) && batch >= 1 && n_in >= 1 && n_out >= 1 &&
+           (act == BSE_ACT_NONE || act == BSE_ACT_GELU);
+}
+
 }  // namespace bse
 
 using namespace bse;
@@ -252,22 +306,31 @@ bse_status bse_dense_forward(const float* x, const float* W, const float* b, flo
 bse_status bse_dense_backward(const float* x, const float* W, const float* z, const float* dy, float* dx, float* dW,
                               float* db, int32_t batch, int32_t n_in, int32_t n_out, int32_t act, float* work,
                               hipStream_t stream) {
-    if (!x || !W || !dy || !dW || !db || !work || (act == BSE_ACT_GELU && !z) || batch < 1 || n_in < 1 ||
-        n_out < 1 || (act != BSE_ACT_NONE && act != BSE_ACT_GELU)) {
+    if (!work || !dense_backward_args_ok(x, W, z, dy, dW, db, batch, n_in, n_out, act)) {
         set_error("bse_dense_backward: NULL array, empty size or unknown activation");
         return BSE_ERR_INVALID_ARG;
     }
-    const int64_t n = (int64_t)batch * n_out;
-    hipLaunchKernelGGL(k_act_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, z, dy, work, n, act);
-    // dW [n_out][n_in] = dz^T x ; db = column sums of dz ; dx [batch][n_in] = dz W
-    hipLaunchKernelGGL((k_gemm<true, false>), dim3((n_in + kTile - 1) / kTile, (n_out + kTile - 1) / kTile), dim3(256),
-                       0, stream, work, x, nullptr, nullptr, dW, n_out, n_in, batch, (int)BSE_ACT_NONE);
-    hipLaunchKernelGGL(k_colsum, dim3((n_out + 255) / 256), dim3(256), 0, stream, work, db, batch, n_out);
-    if (dx)
-        hipLaunchKernelGGL((k_gemm<false, false>), dim3((n_in + kTile - 1) / kTile, (batch + kTile - 1) / kTile),
-                           dim3(256), 0, stream, work, W, nullptr, nullptr, dx, batch, n_in, n_out, (int)BSE_ACT_NONE);
-    const hipError_t e = hipGetLastError();
+    const hipError_t e = enqueue_dense_backward(x, W, z, dy, dx, dW, db, batch, n_in, n_out, act, work, stream);
     return e == hipSuccess ? BSE_OK : fail(e, "bse_dense_backward");
+}
+
+bse_status bse_dense_backward_noalloc(const float* x, const float* W, const float* z, const float* dy, float* dx,
+                                      float* dW, float* db, int32_t batch, int32_t n_in, int32_t n_out, int32_t act,
+                                      hipStream_t stream) {
+    if (!dense_backward_args_ok(x, W, z, dy, dW, db, batch, n_in, n_out, act)) {
+        set_error("bse_dense_backward_noalloc: NULL array, empty size or unknown activation");
+        return BSE_ERR_INVALID_ARG;
+    }
+    if ((int64_t)batch * n_out > kNoAllocMaxEntries) {
+        set_error("bse_dense_backward_noalloc: batch * n_out = %lld exceeds the scratch limit %lld",
+                  (long long)batch * n_out, (long long)kNoAllocMaxEntries);
+        return BSE_ERR_WORKSPACE;
+    }
+    float* work = nullptr;
+    hipError_t e = scratch_address(&work);
+    if (e != hipSuccess) return fail(e, "bse_dense_backward_noalloc: scratch address");
+    e = enqueue_dense_backward(x, W, z, dy, dx, dW, db, batch, n_in, n_out, act, work, stream);
+    return e == hipSuccess ? BSE_OK : fail(e, "bse_dense_backward_noalloc");
 }
 
 bse_status bse_mse_loss(const float* y, const float* t, float* dy, double* loss, int64_t n, hipStream_t stream) {

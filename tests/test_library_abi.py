@@ -114,3 +114,12 @@ def test_m3_band_geometry_and_checks(bse):
     assert lib.bse_plan_set_m3_band(None, None, 1.0) == bse.BSE_ERR_INVALID_ARG
     assert lib.bse_build_divergence_coefficient(ctypes.byref(d), None, 1, ctypes.byref(m), 1, None) == bse.BSE_ERR_INVALID_ARG
 
+
+
+def test_noalloc_backward_rejects_oversized_calls_before_device_work(bse):
+    lib = bse.library()
+    # non-NULL dummy pointers: the size check comes before any device call
+    st = lib.bse_dense_backward_noalloc(8, 8, 8, 8, 8, 8, 8, (1 << 20) // 64 + 1, 8, 64, bse.BSE_ACT_GELU, None)
+    assert st == bse.BSE_ERR_WORKSPACE
+    st = lib.bse_dense_backward_noalloc(None, 8, 8, 8, 8, 8, 8, 4, 8, 64, bse.BSE_ACT_GELU, None)
+    assert st == bse.BSE_ERR_INVALID_ARG
