@@ -174,8 +174,10 @@ bse_status bse_build_coarse_kernel(const bse_dims* dims, const double* vecs_coar
  *              Besides scratch space it holds the restrict tiles: a copy of d
  *              re-ordered for the restrict kernel, with the valence blocks already
  *              multiplied by the prefactors f (Sec. 3); for BSE_BF16_KC and
- *              BSE_F16_KC also the block-scaled copy of Kc (Kc itself is then not
- *              read after plan creation).
+ *              BSE_F16_KC also the block-scaled copy of Kc, and for BSE_F32 and
+ *              BSE_F32_VEC64 the packed copy of its 128 x 128 tiles on and above the
+ *              diagonal (Kc itself is then not read after plan creation unless
+ *              bse_plan_set_coarse_product selects the full stream).
  *   stream     the copies are written by kernels enqueued on this stream; later
  *              calls on the plan must be ordered after them (same stream, or
  *              synchronised).
@@ -373,6 +375,14 @@ bse_status bse_plan_set_m3_band(bse_plan* plan, void* band, double w);
 
 /* Tunables of the coarse product: column splits (0 = automatic).  For sweeps. */
 bse_status bse_plan_set_gemv_splits(bse_plan* plan, int32_t n_split);
+
+/* Coarse product of Eq. (matmul2) for the FP32 coarse kernel (BSE_F32, BSE_F32_VEC64):
+ * form 0 (default) reads the plan's packed copy of the tiles on and above the diagonal
+ * (K_c is Hermitian, Eqs. bse1-bse2: half the bytes), with FP32 products and FP32 sums
+ * over runs of 16 tile columns (32 rows for the conjugate-transposed tiles) added in
+ * FP64; form 1 streams the whole Kc with FP64 products and sums.  Ignored by the other
+ * precisions.  For comparisons and sweeps. */
+bse_status bse_plan_set_coarse_product(bse_plan* plan, int32_t form);
 
 /* Tunable of the restrict (Eq. matmul1): right-hand sides handled by one block, 1
  * (default) or 3 (used only when a call has exactly three right-hand sides).  Both

@@ -39,7 +39,7 @@ EXPORTED = [
     "bse_overlaps_bytes", "bse_build_overlaps", "bse_build_transition_energies",
     "bse_build_coarse_kernel", "bse_plan_create", "bse_plan_destroy", "bse_interp_matvec",
     "bse_haydock_run", "bse_continued_fraction", "bse_plan_set_timing", "bse_plan_get_timing",
-    "bse_plan_set_gemv_splits", "bse_plan_set_restrict_group", "bse_batch_create", "bse_batch_launch",
+    "bse_plan_set_gemv_splits", "bse_plan_set_coarse_product", "bse_plan_set_restrict_group", "bse_batch_create", "bse_batch_launch",
     "bse_batch_destroy", "bse_dense_forward", "bse_dense_backward", "bse_dense_backward_noalloc", "bse_mse_loss", "bse_adam_step",
     "bse_to_bf16", "bse_dense_forward_bf16", "bse_continued_fraction_terminated",
     "bse_build_divergence_coefficient", "bse_m3_band_info", "bse_build_m3_band", "bse_plan_set_m3_band",
@@ -86,6 +86,7 @@ def _load():
         "bse_plan_set_timing": (i32, [vp, i32]),
         "bse_plan_get_timing": (i32, [vp, P(dbl), P(i64)]),
         "bse_plan_set_gemv_splits": (i32, [vp, i32]),
+        "bse_plan_set_coarse_product": (i32, [vp, i32]),
         "bse_plan_set_restrict_group": (i32, [vp, i32]),
         "bse_batch_create": (i32, [P(vp), i32, P(vp), P(i32), i32, P(vp), P(vp), P(vp), P(vp), P(vp), i32, P(vp)]),
         "bse_batch_launch": (i32, [vp, vp]),
@@ -216,6 +217,11 @@ def bse_plan_get_timing(plan):
 
 def bse_plan_set_gemv_splits(plan, n_split: int):
     _check(_lib.bse_plan_set_gemv_splits(plan, int(n_split)), "bse_plan_set_gemv_splits")
+
+
+def bse_plan_set_coarse_product(plan, form: int):
+    """0: packed Hermitian tiles (default for the FP32 coarse kernel); 1: full stream."""
+    _check(_lib.bse_plan_set_coarse_product(plan, int(form)), "bse_plan_set_coarse_product")
 
 
 def bse_plan_set_restrict_group(plan, rhs_per_block: int):

@@ -141,6 +141,15 @@ Layout make_layout(const Geometry& g) {
         L.kscale = take(L.kscale_bytes);
         L.qfrag = take(L.qfrag_bytes);
     }
+    L.kp = L.hpart = L.htab = off;
+    L.kp_bytes = 0;
+    if (kc_packable(g.dtype)) {
+        const HemvShape h = hemv_shape(g.Nc);
+        L.kp_bytes = (size_t)h.tiles * h.tile_bytes;
+        L.kp = take(L.kp_bytes);
+        L.hpart = take((size_t)(h.blocks + h.tiles) * 128 * R * sizeof(float2));
+        L.htab = take((size_t)(h.blocks + h.nbk + 1) * sizeof(int));
+    }
     L.dsw_bytes = 0;
     L.dsw = off;
     if (supported_bands(g.nv, g.nc) && restrict_tile_lds(g) > 0) {
@@ -333,6 +342,7 @@ bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d, 
     p->delta = delta;
     p->ws = static_cast<char*>(workspace);
     p->n_split = 0;
+    p->product_form = 0;
     p->restrict_group = 1;
     p->timing = 0;
     p->ev = nullptr;
@@ -344,6 +354,7 @@ bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d, 
     // low-precision forms also the block-scaled coarse kernel
     hipError_t e = launch_swizzle(*p, stream);
     if (e == hipSuccess) e = launch_quantize(*p, stream);
+    if (e == hipSuccess) e = launch_hemv_pack(*p, stream);
     if (e != hipSuccess) {
         delete p;
         return hip_fail(e, "bse_plan_create");
@@ -486,6 +497,15 @@ bse_status bse_plan_set_gemv_splits(bse_plan* plan, int32_t n_split) {
         return BSE_ERR_INVALID_ARG;
     }
     reinterpret_cast<Plan*>(plan)->n_split = n_split;
+    return BSE_OK;
+}
+
+bse_status bse_plan_set_coarse_product(bse_plan* plan, int32_t form) {
+    if (!plan || (form != 0 && form != 1)) {
+        set_error("bse_plan_set_coarse_product: form must be 0 (packed Hermitian tiles) or 1 (full stream)");
+        return BSE_ERR_INVALID_ARG;
+    }
+    reinterpret_cast<Plan*>(plan)->product_form = form;
     return BSE_OK;
 }
 

@@ -85,12 +85,23 @@ inline bool kc_lowp(int dtype) { return dtype == BSE_BF16_KC || dtype == BSE_F16
 // Lanczos vectors in FP32 storage
 inline bool vec_is_f32(int dtype) { return dtype == BSE_F32 || kc_lowp(dtype); }
 
+// Packed Hermitian coarse product (FP32 coarse kernel): 128 x 128 tiles on and above the
+// diagonal, their partial sums and the block table (see gemv.hip)
+struct HemvShape {
+    int nbk;            // tile rows: ceil(Nc / 128)
+    int64_t tiles;      // nbk (nbk + 1) / 2
+    int64_t blocks;     // groups of 4 tiles of one tile row
+    size_t tile_bytes;  // 128 x 128 complex FP32
+};
+HemvShape hemv_shape(int64_t Nc);
+inline bool kc_packable(int dtype) { return dtype == BSE_F32 || dtype == BSE_F32_VEC64; }
+
 // workspace regions (byte offsets from the workspace base); dsw_bytes == 0 when the
 // restrict reads the overlaps in their input layout; kq, kscale, qfrag only for the
-// low-precision forms
+// low-precision forms; kp, hpart, htab only for the FP32 coarse kernel
 struct Layout {
-    size_t qpart, qbar, rvec, gpart, ppart, rpart, chain, pend, vec_a, vec_b, dsw, kq, kscale, qfrag;
-    size_t dsw_bytes, kq_bytes, kscale_bytes, qfrag_bytes;
+    size_t qpart, qbar, rvec, gpart, ppart, rpart, chain, pend, vec_a, vec_b, dsw, kq, kscale, qfrag, kp, hpart, htab;
+    size_t dsw_bytes, kq_bytes, kscale_bytes, qfrag_bytes, kp_bytes;
     size_t total;
 };
 Layout make_layout(const Geometry& g);
@@ -103,6 +114,7 @@ struct Plan {
     const double* delta;
     char* ws;
     int n_split;  // 0 = automatic
+    int product_form;  // coarse product of the FP32 coarse kernel: 0 packed Hermitian tiles, 1 full stream
     int restrict_group;  // right-hand sides per restrict block (1, or 3 for three)
     // kernel timing: 0 off, 1 the coarse product, 2 the Method 3 band product
     int timing;
@@ -136,6 +148,9 @@ hipError_t launch_m3_apply(Plan& p, const void* x, int n_rhs, hipStream_t s);
 hipError_t launch_swizzle(const Plan& p, hipStream_t s);
 // block-scaled coarse kernel and cleared qbar fragments (gemv.hip), at plan creation
 hipError_t launch_quantize(const Plan& p, hipStream_t s);
+// packed Hermitian tiles and their block table (gemv.hip), at plan creation
+hipError_t launch_hemv_pack(const Plan& p, hipStream_t s);
+inline bool use_packed(const Plan& p) { return p.L.kp_bytes > 0 && p.product_form == 0; }
 // vector slice of a cell held in LDS by the tiled restrict: bytes, or 0 if it does not fit
 size_t restrict_tile_lds(const Geometry& g);
 

@@ -467,6 +467,328 @@ static hipError_t gemv_lowp(Plan& p, int n_rhs, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---- packed Hermitian product (FP32 coarse kernel) -------------------------------------
+//
+// K_c is Hermitian (Eqs. bse1-bse2), so its 128 x 128 tiles (I, J) with I <= J hold all of
+// it: half the bytes of the full stream.  One wavefront streams one tile and does both
+// products the tile serves,
+//   P1: r_I += K_IJ q_J          (rows of the tile),
+//   P2: r_J += K_IJ^H q_I        (columns; not on the diagonal tile, which P1 covers whole).
+// Lane L owns tile rows L and 64 + L.  At step s of column half h it holds column
+// 64 h + (L + s) mod 64 of both rows: one 16-byte load of two complex FP32 entries, and the
+// tile is stored in that order, so every load instruction of the wavefront reads one
+// contiguous 1 KiB run.  P1 accumulates per lane (its rows).  P2's partial of a column
+// moves one lane per step with a DPP wavefront rotate, so each lane adds into the column it
+// holds; after 64 steps every partial is back on the lane of its column.
+// Arithmetic: products and sums in FP32 over runs of kHemvFlush steps (P1: kHemvFlush terms
+// per row, P2: 2 kHemvFlush terms per column), then added into FP64 (P1 in registers, P2 in
+// LDS).  A block is 4 wavefronts on 4 consecutive tiles of one tile row: their P1 sums are
+// added in LDS in a fixed order and written as one partial of r_I; every off-diagonal tile
+// writes its P2 partial of r_J.  k_hemv_reduce adds, for each output, the partials of its
+// tile row and of its tile column in a fixed order.
+
+constexpr int kHemvTile = 128;
+constexpr int kHemvFlush = 16;   // steps per FP32 run before the FP64 sums
+constexpr int kHemvUnroll = 8;   // 16-byte loads of a lane in flight
+
+__host__ __device__ inline int64_t hemv_tile_index(int I, int J, int nbk) {
+    return (int64_t)I * nbk - (int64_t)I * (I - 1) / 2 + (J - I);
+}
+
+// rotate a float across the wavefront: lane L receives lane L + 1 (mod 64)
+__device__ __forceinline__ float wave_rol1(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134, 0xF, 0xF, false));
+}
+
+// packed tiles from the row-major FP32 K_c: one block per (tile, half, 4 steps)
+__global__ __launch_bounds__(256) void k_hemv_pack(const float2* __restrict__ K, f4v* __restrict__ kp, int64_t Nc,
+                                                   int nbk) {
+    const int64_t unit = blockIdx.x;   // (tile, half, step group of 4)
+    const int64_t tile = unit / 32;
+    const int hs = (int)(unit % 32);
+    const int h = hs / 16, s = (hs % 16) * 4 + threadIdx.x / kWave;
+    const int L = threadIdx.x % kWave;
+    int I = 0;
+    while (I + 1 < nbk && hemv_tile_index(I + 1, I + 1, nbk) <= tile) ++I;
+    const int J = I + (int)(tile - hemv_tile_index(I, I, nbk));
+    const int64_t col = (int64_t)J * kHemvTile + 64 * h + ((L + s) & 63);
+    const int64_t r0 = (int64_t)I * kHemvTile + L, r1 = r0 + 64;
+    const float2 a = (r0 < Nc && col < Nc) ? K[r0 * Nc + col] : make_float2(0.0f, 0.0f);
+    const float2 b = (r1 < Nc && col < Nc) ? K[r1 * Nc + col] : make_float2(0.0f, 0.0f);
+    kp[((tile * 2 + h) * 64 + s) * kWave + L] = f4v{a.x, a.y, b.x, b.y};
+}
+
+// block -> (tile row I, group g of 4 tiles): table[b] = I | g << 16; band0[I] = first block of row I
+__global__ void k_hemv_table(int* __restrict__ table, int* __restrict__ band0, int nbk) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int b = 0;
+    for (int I = 0; I < nbk; ++I) {
+        band0[I] = b;
+        const int ng = (nbk - I + 3) / 4;
+        for (int g = 0; g < ng; ++g) table[b++] = I | (g << 16);
+    }
+    band0[nbk] = b;
+}
+
+// one wavefront streams tile (I, J): P1 row sums into d1 (FP64), P2 (OFFDIAG) into its
+// FP64 column sums in LDS (p2), then the tile's P2 partial of r_J
+template <int NRHS, bool OFFDIAG>
+__device__ __forceinline__ void hemv_tile(const f4v* __restrict__ kp, const float2* qj, double2* p2,
+                                          const float2 (&qi)[2][NRHS], double (&d1)[2][NRHS][2],
+                                          float2* __restrict__ r2part, int I, int J, int nbk, int L) {
+    const f4v* tp = kp + hemv_tile_index(I, J, nbk) * (2 * 64 * kWave) + L;
+    float a1[2][NRHS][2], a2[NRHS][2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) a1[e][r][0] = a1[e][r][1] = 0.0f;
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) a2[r][0] = a2[r][1] = 0.0f;
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll 1
+        for (int sf = 0; sf < 64; sf += kHemvFlush) {
+#pragma unroll
+            for (int s0 = sf; s0 < sf + kHemvFlush; s0 += kHemvUnroll) {
+                f4v kv[kHemvUnroll];
+#pragma unroll
+                for (int u = 0; u < kHemvUnroll; ++u)
+                    kv[u] = __builtin_nontemporal_load(tp + (int64_t)((h * 64 + s0 + u) * kWave));
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < kHemvUnroll; ++u) {
+                    // keep each step's LDS reads next to its arithmetic
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int s = s0 + u;
+                    const int c = 64 * h + ((L + s) & 63);
+                    const float k0r = kv[u].x, k0i = kv[u].y, k1r = kv[u].z, k1i = kv[u].w;
+#pragma unroll
+                    for (int r = 0; r < NRHS; ++r) {
+                        const float2 q = qj[r * kHemvTile + c];
+                        // P1: row L and row 64 + L times q_J[c]
+                        a1[0][r][0] = fmaf(k0r, q.x, a1[0][r][0]);
+                        a1[0][r][0] = fmaf(-k0i, q.y, a1[0][r][0]);
+                        a1[0][r][1] = fmaf(k0r, q.y, a1[0][r][1]);
+                        a1[0][r][1] = fmaf(k0i, q.x, a1[0][r][1]);
+                        a1[1][r][0] = fmaf(k1r, q.x, a1[1][r][0]);
+                        a1[1][r][0] = fmaf(-k1i, q.y, a1[1][r][0]);
+                        a1[1][r][1] = fmaf(k1r, q.y, a1[1][r][1]);
+                        a1[1][r][1] = fmaf(k1i, q.x, a1[1][r][1]);
+                    }
+                    if (OFFDIAG) {
+                        // P2: column c gets conj(K[L][c]) q_I[L] + conj(K[64 + L][c]) q_I[64 + L]
+#pragma unroll
+                        for (int r = 0; r < NRHS; ++r) {
+                            float re = a2[r][0], im = a2[r][1];
+                            re = fmaf(k0r, qi[0][r].x, re);
+                            re = fmaf(k0i, qi[0][r].y, re);
+                            re = fmaf(k1r, qi[1][r].x, re);
+                            re = fmaf(k1i, qi[1][r].y, re);
+                            im = fmaf(k0r, qi[0][r].y, im);
+                            im = fmaf(-k0i, qi[0][r].x, im);
+                            im = fmaf(k1r, qi[1][r].y, im);
+                            im = fmaf(-k1i, qi[1][r].x, im);
+                            // the partial moves on with its column: lane L now holds
+                            // column 64 h + (L + s + 1) mod 64
+                            a2[r][0] = wave_rol1(re);
+                            a2[r][1] = wave_rol1(im);
+                        }
+                    }
+                }
+            }
+            // end of a run: FP32 sums into FP64
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+#pragma unroll
+                for (int r = 0; r < NRHS; ++r) {
+                    d1[e][r][0] += (double)a1[e][r][0];
+                    d1[e][r][1] += (double)a1[e][r][1];
+                    a1[e][r][0] = a1[e][r][1] = 0.0f;
+                }
+            if (OFFDIAG) {
+                // the P2 sums of a column are read and written by different lanes at
+                // different runs: keep this wavefront's LDS accesses in order
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                const int cn = 64 * h + ((L + sf + kHemvFlush) & 63);
+#pragma unroll
+                for (int r = 0; r < NRHS; ++r) {
+                    double2 v = p2[r * kHemvTile + cn];
+                    v.x += (double)a2[r][0];
+                    v.y += (double)a2[r][1];
+                    p2[r * kHemvTile + cn] = v;
+                    a2[r][0] = a2[r][1] = 0.0f;
+                }
+            }
+        }
+    }
+    // P2 partial of r_J: this tile's 128 columns (the last flush of each half left
+    // column 64 h + L on lane L)
+    if (OFFDIAG) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        float2* out = r2part + hemv_tile_index(I, J, nbk) * kHemvTile * NRHS;
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int r = 0; r < NRHS; ++r) {
+                const double2 v = p2[r * kHemvTile + 64 * e + L];
+                out[(64 * e + L) * NRHS + r] = make_float2((float)v.x, (float)v.y);
+            }
+    }
+}
+
+template <int NRHS>
+__global__ __launch_bounds__(256, 4) void k_hemv(const f4v* __restrict__ kp, const double2* __restrict__ qbar,
+                                                 const int* __restrict__ table, float2* __restrict__ r1part,
+                                                 float2* __restrict__ r2part, int Nc, int nbk) {
+    extern __shared__ double2 hsm[];
+    const int wave = threadIdx.x / kWave;
+    const int L = threadIdx.x % kWave;
+    const int code = table[blockIdx.x];
+    const int I = code & 0xffff, g = code >> 16;
+    const int J = I + 4 * g + wave;
+    const bool active = J < nbk;       // wavefront-uniform
+    const bool offdiag = J != I;
+    // LDS: q_J of each wavefront [4][NRHS][128] (float2), then the FP64 P2 sums [4][NRHS][128]
+    float2* qj = reinterpret_cast<float2*>(hsm) + wave * NRHS * kHemvTile;
+    double2* p2 = hsm + 4 * NRHS * kHemvTile / 2 + wave * NRHS * kHemvTile;
+    // q_I of this lane's two rows (FP32) and q_J of the tile's columns in LDS
+    float2 qi[2][NRHS];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int row = I * kHemvTile + 64 * e + L;
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) {
+            const double2 q = row < Nc ? qbar[(int64_t)row * NRHS + r] : make_double2(0.0, 0.0);
+            qi[e][r] = make_float2((float)q.x, (float)q.y);
+        }
+    }
+    if (active) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int col = J * kHemvTile + 64 * e + L;
+#pragma unroll
+            for (int r = 0; r < NRHS; ++r) {
+                const double2 q = col < Nc ? qbar[(int64_t)col * NRHS + r] : make_double2(0.0, 0.0);
+                qj[r * kHemvTile + 64 * e + L] = make_float2((float)q.x, (float)q.y);
+                p2[r * kHemvTile + 64 * e + L] = make_double2(0.0, 0.0);
+            }
+        }
+    }
+    __syncthreads();
+    double d1[2][NRHS][2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) d1[e][r][0] = d1[e][r][1] = 0.0;
+    if (active) {
+        if (offdiag)
+            hemv_tile<NRHS, true>(kp, qj, p2, qi, d1, r2part, I, J, nbk, L);
+        else
+            hemv_tile<NRHS, false>(kp, qj, p2, qi, d1, r2part, I, J, nbk, L);
+    }
+    // P1 partial of r_I: the 4 wavefronts' row sums added in LDS in a fixed order
+    __syncthreads();
+    double2* red = hsm + 4 * NRHS * kHemvTile / 2;   // [4][128][NRHS], over the P2 sums
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r)
+            red[(wave * kHemvTile + 64 * e + L) * NRHS + r] = make_double2(d1[e][r][0], d1[e][r][1]);
+    __syncthreads();
+    for (int o = threadIdx.x; o < kHemvTile * NRHS; o += blockDim.x) {
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const double2 v = red[w * kHemvTile * NRHS + o];
+            re += v.x;
+            im += v.y;
+        }
+        r1part[(int64_t)blockIdx.x * kHemvTile * NRHS + o] = make_float2((float)re, (float)im);
+    }
+}
+
+// r[i][rhs] = sum of the P1 partials of tile row b = i / 128 (its blocks in order), then of
+// the P2 partials of tiles (I, b), I < b, in order of I
+template <int NRHS>
+__global__ __launch_bounds__(256) void k_hemv_reduce(const float2* __restrict__ r1part,
+                                                     const float2* __restrict__ r2part, const int* __restrict__ band0,
+                                                     double2* __restrict__ rout, int Nc, int nbk) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= (int64_t)Nc * NRHS) return;
+    const int i = (int)(o / NRHS), r = (int)(o % NRHS);
+    const int b = i / kHemvTile, w = i % kHemvTile;
+    const int p0 = band0[b], np1 = band0[b + 1] - p0;
+    const int n = np1 + b;   // P1 partials, then P2 partials of tiles (0, b) .. (b - 1, b)
+    double re = 0.0, im = 0.0;
+    for (int t0 = 0; t0 < n; t0 += 8) {
+        float2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = min(t0 + u, n - 1);
+            const int64_t src = t < np1 ? (int64_t)(p0 + t) : hemv_tile_index(t - np1, b, nbk);
+            v[u] = (t < np1 ? r1part : r2part)[(src * kHemvTile + w) * NRHS + r];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (t0 + u < n) {
+                re += (double)v[u].x;
+                im += (double)v[u].y;
+            }
+    }
+    rout[o] = make_double2(re, im);
+}
+
+HemvShape hemv_shape(int64_t Nc) {
+    HemvShape h;
+    h.nbk = (int)((Nc + kHemvTile - 1) / kHemvTile);
+    h.tiles = (int64_t)h.nbk * (h.nbk + 1) / 2;
+    int64_t b = 0;
+    for (int I = 0; I < h.nbk; ++I) b += (h.nbk - I + 3) / 4;
+    h.blocks = b;
+    h.tile_bytes = (size_t)kHemvTile * kHemvTile * sizeof(float2);
+    return h;
+}
+
+hipError_t launch_hemv_pack(const Plan& p, hipStream_t s) {
+    if (p.L.kp_bytes == 0) return hipSuccess;
+    const HemvShape h = hemv_shape(p.g.Nc);
+    hipLaunchKernelGGL(k_hemv_pack, dim3((unsigned)(h.tiles * 32)), dim3(kBlock), 0, s,
+                       reinterpret_cast<const float2*>(p.Kc), reinterpret_cast<f4v*>(p.ws + p.L.kp), p.g.Nc, h.nbk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hemv_table, dim3(1), dim3(kWave), 0, s, reinterpret_cast<int*>(p.ws + p.L.htab),
+                       reinterpret_cast<int*>(p.ws + p.L.htab) + h.blocks, h.nbk);
+    return hipGetLastError();
+}
+
+template <int NRHS>
+static hipError_t hemv_t(Plan& p, hipStream_t s) {
+    const Geometry& g = p.g;
+    const HemvShape h = hemv_shape(g.Nc);
+    const int* tab = reinterpret_cast<const int*>(p.ws + p.L.htab);
+    float2* r1 = reinterpret_cast<float2*>(p.ws + p.L.hpart);
+    float2* r2 = r1 + (size_t)h.blocks * kHemvTile * NRHS;
+    const size_t lds = (size_t)4 * NRHS * kHemvTile * (sizeof(float2) + sizeof(double2));
+    hipLaunchKernelGGL((k_hemv<NRHS>), dim3((unsigned)h.blocks), dim3(kBlock), lds, s,
+                       reinterpret_cast<const f4v*>(p.ws + p.L.kp), reinterpret_cast<const double2*>(p.ws + p.L.qbar),
+                       tab, r1, r2, (int)g.Nc, h.nbk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n_out = g.Nc * NRHS;
+    hipLaunchKernelGGL((k_hemv_reduce<NRHS>), dim3((unsigned)((n_out + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, r1,
+                       r2, tab + h.blocks, reinterpret_cast<double2*>(p.ws + p.L.rvec), (int)g.Nc, h.nbk);
+    return hipGetLastError();
+}
+
+static hipError_t hemv_r(Plan& p, int n_rhs, hipStream_t s) {
+    switch (n_rhs) {
+        case 1: return hemv_t<1>(p, s);
+        case 2: return hemv_t<2>(p, s);
+        case 3: return hemv_t<3>(p, s);
+        default: return hemv_t<4>(p, s);
+    }
+}
+
 template <class M2>
 static hipError_t gemv_r(Plan& p, int n_rhs, hipStream_t s) {
     switch (n_rhs) {
@@ -487,6 +809,7 @@ hipError_t launch_gemv(Plan& p, int n_rhs, hipStream_t s) {
     }
     hipError_t err = kc_lowp(p.g.dtype)        ? gemv_lowp(p, n_rhs, s)
                      : (p.g.dtype == BSE_F64) ? gemv_r<double2>(p, n_rhs, s)
+                     : use_packed(p)          ? hemv_r(p, n_rhs, s)
                                               : gemv_r<float2>(p, n_rhs, s);
     if (e1) (void)hipEventRecord(e1, s);
     return err;

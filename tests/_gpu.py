@@ -32,12 +32,36 @@ def abs_operator(op: O.InterpOperator) -> O.InterpOperator:
                             np.abs(op.Kc).astype(complex), np.abs(op.delta), op.n_c, op.n_div, op.nv, op.nc)
 
 
-def product_bound(op: O.InterpOperator, x, unit: float, factors: int = 10):
+# The packed Hermitian coarse product of the FP32 coarse kernel (the library's default for
+# BSE_F32 and BSE_F32_VEC64) computes r = K_c qbar in FP32 arithmetic: qbar is rounded to
+# FP32 (1 unit of |qbar|), each FP32 run adds at most 64 FMA terms into one accumulator
+# (conjugate-transposed tiles: 16 steps x 2 rows x 2 FMAs per component; plain tiles:
+# 16 x 2), which the first-order bound of recursive summation keeps within 64 units of the
+# run's sum of |terms|; runs are added in FP64 and each tile partial is rounded to FP32 once
+# (1 unit).  Every output of r is therefore within 66 units of sum_j |K_ij| |qbar_j|, and
+# the prolong carries that to |C|^H |K| |C| |x| on top of the 10 units of storage rounding.
+PACKED_PRODUCT_UNITS = 66
+
+
+def product_bound(op: O.InterpOperator, x, unit: float, factors: int = 10, kernel_factors=None):
     """Componentwise bound on |y_gpu - y| for storage rounding of unit `unit`.
 
     Every term of y = delta x + C^H K C x is a product of at most 7 stored
     factors (x, 2 overlaps, K_c, 2 overlaps, output); FP64 accumulation adds
     well below one FP32 unit.  `factors` units per |term| covers that.
+    kernel_factors (default: factors) applies to the kernel terms C^H K C x alone,
+    for products whose arithmetic adds its own rounding (PACKED_PRODUCT_UNITS).
     """
     aop = abs_operator(op)
-    return factors * unit * np.abs(aop.apply(np.abs(x)))
+    ax = np.abs(x)
+    if kernel_factors is None:
+        return factors * unit * np.abs(aop.apply(ax))
+    diag = np.abs(aop.delta)[None] * np.atleast_2d(ax)
+    kern = aop.apply_kernel(ax)
+    return unit * (factors * diag + kernel_factors * np.abs(kern))
+
+
+def fp32_kernel_factors(packed: bool) -> int:
+    """Units of the kernel terms for the FP32 coarse kernel: storage rounding (10), plus the
+    packed product's own arithmetic when it runs (form 0)."""
+    return 10 + (PACKED_PRODUCT_UNITS if packed else 0)

@@ -26,7 +26,8 @@ def oracle_pieces(cfg, bs):
 
 def check_sampled_cells(cfg, bs, prob, pieces, cells, seed, unit, factors, rel, n_rhs=3):
     """y = H^i x of `prob` on the dense points of `cells` against the oracle, within
-    `factors` units `unit` of the sum of |terms| of each output, and `rel` in relative L2."""
+    `factors` units `unit` of the sum of |terms| of each output (or (diagonal, kernel)
+    units for the two kinds of terms), and `rel` in relative L2."""
     Dv, Dc, delta = pieces
     f = O.trilinear_weights(cfg.n_div)
     x = prob.vector(ti.random_vectors(cfg.n_trans, n_rhs, seed))
@@ -47,7 +48,8 @@ def check_sampled_cells(cfg, bs, prob, pieces, cells, seed, unit, factors, rel, 
         r[:, k * np_:(k + 1) * np_] = (rows[i] @ qbar.T).T
         rabs[:, k * np_:(k + 1) * np_] = (np.abs(rows[i]) @ np.abs(qabs).T).T
     ref = delta[None] * xh + op.prolong(r)
-    bound = factors * unit * np.abs(np.abs(delta)[None] * np.abs(xh) + aop.prolong(rabs))
+    fd, fk = factors if isinstance(factors, tuple) else (factors, factors)
+    bound = unit * (fd * np.abs(delta)[None] * np.abs(xh) + fk * np.abs(aop.prolong(rabs)))
     ndiv3 = cfg.n_div3
     for cell in cells:
         sl = slice(cell * ndiv3 * np_, (cell + 1) * ndiv3 * np_)

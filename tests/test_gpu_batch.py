@@ -10,7 +10,7 @@ import oracle as O
 import tbinputs as ti
 
 from _cases import bands, oracle_operator, oracle_parts, rel_l2
-from _gpu import U32
+from _gpu import U32, fp32_kernel_factors
 from _sampled import check_sampled_cells, oracle_pieces
 
 pytestmark = pytest.mark.gpu
@@ -172,8 +172,9 @@ def test_batch_workload_shapes_against_the_oracle(bse, cfg):
     """The two larger grid shapes of the 48-member batching workload, one member each
     (6^3 x 3 displaced by +delta with 3v3c; 8^3 x 4 displaced by -delta with 3v6c), in
     FP32 storage as the workload runs them:
-    * sampled matvec cells against the oracle, within 10 FP32 units of the sum of
-      |terms| of each output and 2e-6 in relative L2;
+    * sampled matvec cells against the oracle, within the FP32 bound of each output's
+      sum of |terms| (storage rounding, and the packed coarse product's arithmetic on the
+      kernel terms) and 2e-6 in relative L2;
     * the member's chains run in a batch (200 steps, 3 polarisations) against the
       oracle's FP64 chain head to 1e-6, up to two steps before the oracle's
       complex64-storage emulation first departs from FP64 by more than 1e-6 (at
@@ -181,7 +182,8 @@ def test_batch_workload_shapes_against_the_oracle(bse, cfg):
     bs = bands(cfg)
     prob = bse.problem_from_bands(bs, cfg, dtype="f32", max_rhs=3)
     cells = np.array([0, cfg.nk_coarse // 3, cfg.nk_coarse - 1])
-    check_sampled_cells(cfg, bs, prob, oracle_pieces(cfg, bs), cells, 301, U32, 10, 2e-6)
+    check_sampled_cells(cfg, bs, prob, oracle_pieces(cfg, bs), cells, 301, U32, (10, fp32_kernel_factors(True)),
+                        2e-6)
     P = bs.P_flat()
     batch = bse.BSEBatch([prob], [P], 200, n_branches=1)
     got = _host(batch.run()[0])

@@ -18,7 +18,7 @@ import oracle as O
 import tbinputs as ti
 
 from _cases import bands, rel_l2
-from _gpu import U32, U64, gpu_overlaps_to_oracle
+from _gpu import U32, U64, fp32_kernel_factors, gpu_overlaps_to_oracle
 from _sampled import check_sampled_cells
 
 pytestmark = pytest.mark.gpu
@@ -88,9 +88,15 @@ def _sampled_cells(bs, prob, pieces, seed, unit, factors, rel):
     check_sampled_cells(CFG, bs, prob, pieces, SAMPLE_CELLS, seed, unit, factors, rel)
 
 
-def test_c1_matvec_sampled_cells(c1, c1_oracle_pieces):
+@pytest.mark.parametrize("form", [0, 1], ids=["packed", "full"])
+def test_c1_matvec_sampled_cells(bse, c1, c1_oracle_pieces, form):
+    """Both coarse products of the FP32 coarse kernel in the benchmark's launch
+    configuration: the packed Hermitian tiles (default) within the bound of their FP32
+    arithmetic, the full stream within storage rounding."""
     bs, prob = c1
-    _sampled_cells(bs, prob, c1_oracle_pieces, 201, U32, 10, 2e-6)
+    bse.bse_plan_set_coarse_product(prob.plan, form)
+    _sampled_cells(bs, prob, c1_oracle_pieces, 201, U32, (10, fp32_kernel_factors(form == 0)), 2e-6)
+    bse.bse_plan_set_coarse_product(prob.plan, 0)
 
 
 def test_c1_fp64_matvec_sampled_cells_and_chain_head(bse, c1_oracle_pieces):

@@ -13,7 +13,7 @@ import oracle as O
 import tbinputs as ti
 
 from _cases import bands, oracle_operator, oracle_parts, rel_l2
-from _gpu import U32, U64, gpu_overlaps_to_oracle, product_bound
+from _gpu import U32, U64, fp32_kernel_factors, gpu_overlaps_to_oracle, product_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -87,16 +87,18 @@ def test_matvec_fp64_matches_oracle(bse, cfg):
     prob.close()
 
 
+@pytest.mark.parametrize("form", [0, 1], ids=["packed", "full"])
 @pytest.mark.parametrize("dtype", ["f32", "f32v64"])
 @pytest.mark.parametrize("cfg", CASES, ids=IDS)
-def test_matvec_fp32_storage_within_rounding_bound(bse, cfg, dtype):
+def test_matvec_fp32_storage_within_rounding_bound(bse, cfg, dtype, form):
     op = oracle_operator(cfg)
     prob = _problem(bse, cfg, dtype)
+    bse.bse_plan_set_coarse_product(prob.plan, form)
     x = ti.random_vectors(op.N, cfg.n_pol, 102)
     xs = prob.vector(x)                       # rounded to the vector storage
     y = prob.matvec(xs).cpu().numpy().astype(complex)
     ref = op.apply(xs.cpu().numpy().astype(complex))
-    bound = product_bound(op, x, U32)
+    bound = product_bound(op, x, U32, 10, fp32_kernel_factors(form == 0))
     assert np.all(np.abs(y - ref) <= bound)
     assert rel_l2(y, ref) < 2e-6
     prob.close()
@@ -144,8 +146,10 @@ PATH_CASES = [(ODD_NC, "f32"), (ODD_NC, "f64"), (ti.get_config("c0").with_(n_pol
 @pytest.mark.parametrize("splits", [1, 2, 0])
 @pytest.mark.parametrize("n_rhs", [3, 4])
 def test_matvec_product_paths_match_oracle(bse, cfg, dtype, splits, n_rhs):
+    """The full-stream coarse product (its split and staging paths)."""
     op = oracle_operator(cfg)
     prob = _problem(bse, cfg, dtype)
+    bse.bse_plan_set_coarse_product(prob.plan, 1)
     bse.bse_plan_set_gemv_splits(prob.plan, splits)
     x = ti.random_vectors(op.N, n_rhs, 108)
     xs = prob.vector(x)
@@ -156,6 +160,34 @@ def test_matvec_product_paths_match_oracle(bse, cfg, dtype, splits, n_rhs):
     else:
         assert np.all(np.abs(y - ref) <= product_bound(op, x, U32))
         assert rel_l2(y, ref) < 2e-6
+    prob.close()
+
+
+# the packed Hermitian coarse product: coarse spaces that are not whole 128-row tiles
+# (576 = 4.5 tiles, 1125 = 8.8 tiles, 486 = 3.8 tiles), a single tile row (72 < 128), and
+# every compiled right-hand-side count
+PACKED_CASES = [ti.get_config("c0").with_(n_pol=4), ODD_NC,
+                ti.tiny_config(n_coarse=3, n_div=2, nv=3, nc=6, n_orb=9, seed=17, n_pol=4),
+                ti.tiny_config(n_coarse=2, n_div=3, nv=3, nc=3, n_orb=6, seed=18, n_pol=4)]
+
+
+@pytest.mark.parametrize("cfg", PACKED_CASES, ids=[c.name for c in PACKED_CASES])
+@pytest.mark.parametrize("n_rhs", [1, 2, 3, 4])
+def test_matvec_packed_product_matches_oracle(bse, cfg, n_rhs):
+    """K_c read once per Hermitian pair of tiles (Eqs. bse1-bse2): within storage rounding
+    plus the bound of the product's FP32 arithmetic, and 2e-6 in relative L2; results
+    are reproducible bit for bit."""
+    op = oracle_operator(cfg)
+    prob = _problem(bse, cfg, "f32")
+    x = ti.random_vectors(op.N, n_rhs, 110)
+    xs = prob.vector(x)
+    y = prob.matvec(xs)
+    y2 = prob.matvec(xs)
+    assert torch.equal(y, y2)
+    y = y.cpu().numpy().astype(complex)
+    ref = op.apply(xs.cpu().numpy().astype(complex))
+    assert np.all(np.abs(y - ref) <= product_bound(op, x, U32, 10, fp32_kernel_factors(True)))
+    assert rel_l2(y, ref) < 2e-6
     prob.close()
 
 
@@ -177,7 +209,7 @@ def test_wide_cell_matvec_and_chain_match_oracle(bse, dtype):
     if dtype == "f64":
         assert rel_l2(y, ref) < 1e-13
     else:
-        assert np.all(np.abs(y - ref) <= product_bound(op, x, U32))
+        assert np.all(np.abs(y - ref) <= product_bound(op, x, U32, 10, fp32_kernel_factors(True)))
     # chain start and update forms of the same restrict: the head of the chain
     P = bands(cfg).P_flat()
     och = O.haydock(op.apply, P, cfg.steps)
