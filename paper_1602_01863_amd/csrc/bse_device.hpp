@@ -42,6 +42,67 @@ __device__ __forceinline__ void cfma_jc(cd& acc, cd a, cd b) {
     acc.im = fma(-a.re, b.im, acc.im);
 }
 
+// ---- complex arithmetic in the inner type of a short contraction --------------------
+// The restrict and the prolong form their <= 6-term contractions per (subpoint, corner)
+// in the storage's precision (FP32 for FP32 overlaps, FP64 for FP64) and add the results
+// into FP64 accumulators.
+template <class T>
+struct cplx {
+    T re, im;
+};
+template <class M2>
+struct Inner;
+template <>
+struct Inner<float2> {
+    using t = float;
+};
+template <>
+struct Inner<double2> {
+    using t = double;
+};
+template <class T>
+__device__ __forceinline__ cplx<T> cl(float2 v) {
+    return cplx<T>{(T)v.x, (T)v.y};
+}
+template <class T>
+__device__ __forceinline__ cplx<T> cl(double2 v) {
+    return cplx<T>{(T)v.x, (T)v.y};
+}
+template <class T>
+__device__ __forceinline__ cplx<T> czero() {
+    return cplx<T>{(T)0, (T)0};
+}
+// acc += a * b
+template <class T>
+__device__ __forceinline__ void cmac(cplx<T>& acc, cplx<T> a, cplx<T> b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(a.im, b.re, acc.im);
+}
+// acc += conj(a) * b
+template <class T>
+__device__ __forceinline__ void cmac_cj(cplx<T>& acc, cplx<T> a, cplx<T> b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(-a.im, b.re, acc.im);
+}
+// acc += a * conj(b)
+template <class T>
+__device__ __forceinline__ void cmac_jc(cplx<T>& acc, cplx<T> a, cplx<T> b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(a.im, b.im, acc.re);
+    acc.im = fma(a.im, b.re, acc.im);
+    acc.im = fma(-a.re, b.im, acc.im);
+}
+// FP64 accumulator += inner-precision value
+template <class T>
+__device__ __forceinline__ void cadd_to(cd& acc, cplx<T> v) {
+    acc.re += (double)v.re;
+    acc.im += (double)v.im;
+}
+
 // ---- storage precision ------------------------------------------------------------
 template <class S>
 struct cstore;

@@ -90,7 +90,7 @@ inline bool vec_is_f32(int dtype) { return dtype == BSE_F32 || kc_lowp(dtype); }
 struct HemvShape {
     int nbk;            // tile rows: ceil(Nc / 128)
     int64_t tiles;      // nbk (nbk + 1) / 2
-    int64_t blocks;     // groups of 4 tiles of one tile row
+    int64_t blocks;     // groups of 2 tiles of one tile row
     size_t tile_bytes;  // 128 x 128 complex FP32
 };
 HemvShape hemv_shape(int64_t Nc);

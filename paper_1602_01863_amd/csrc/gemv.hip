@@ -470,8 +470,8 @@ static hipError_t gemv_lowp(Plan& p, int n_rhs, hipStream_t s) {
 // ---- packed Hermitian product (FP32 coarse kernel) -------------------------------------
 //
 // K_c is Hermitian (Eqs. bse1-bse2), so its 128 x 128 tiles (I, J) with I <= J hold all of
-// it: half the bytes of the full stream.  One wavefront streams one tile and does both
-// products the tile serves,
+// it: half the bytes of the full stream.  One wavefront streams one 64-column half of a
+// tile and does both products it serves,
 //   P1: r_I += K_IJ q_J          (rows of the tile),
 //   P2: r_J += K_IJ^H q_I        (columns; not on the diagonal tile, which P1 covers whole).
 // Lane L owns tile rows L and 64 + L.  At step s of column half h it holds column
@@ -482,10 +482,10 @@ static hipError_t gemv_lowp(Plan& p, int n_rhs, hipStream_t s) {
 // holds; after 64 steps every partial is back on the lane of its column.
 // Arithmetic: products and sums in FP32 over runs of kHemvFlush steps (P1: kHemvFlush terms
 // per row, P2: 2 kHemvFlush terms per column), then added into FP64 (P1 in registers, P2 in
-// LDS).  A block is 4 wavefronts on 4 consecutive tiles of one tile row: their P1 sums are
-// added in LDS in a fixed order and written as one partial of r_I; every off-diagonal tile
-// writes its P2 partial of r_J.  k_hemv_reduce adds, for each output, the partials of its
-// tile row and of its tile column in a fixed order.
+// LDS).  A block is 4 wavefronts on the two halves of 2 consecutive tiles of one tile row:
+// their P1 sums are added in LDS in a fixed order and written as one partial of r_I; every
+// off-diagonal tile writes its P2 partial of r_J.  k_hemv_reduce adds, for each output, the
+// partials of its tile row and of its tile column in a fixed order.
 
 constexpr int kHemvTile = 128;
 constexpr int kHemvFlush = 16;   // steps per FP32 run before the FP64 sums
@@ -518,25 +518,26 @@ __global__ __launch_bounds__(256) void k_hemv_pack(const float2* __restrict__ K,
     kp[((tile * 2 + h) * 64 + s) * kWave + L] = f4v{a.x, a.y, b.x, b.y};
 }
 
-// block -> (tile row I, group g of 4 tiles): table[b] = I | g << 16; band0[I] = first block of row I
+// block -> (tile row I, group g of 2 tiles): table[b] = I | g << 16; band0[I] = first block of row I
 __global__ void k_hemv_table(int* __restrict__ table, int* __restrict__ band0, int nbk) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int b = 0;
     for (int I = 0; I < nbk; ++I) {
         band0[I] = b;
-        const int ng = (nbk - I + 3) / 4;
+        const int ng = (nbk - I + 1) / 2;
         for (int g = 0; g < ng; ++g) table[b++] = I | (g << 16);
     }
     band0[nbk] = b;
 }
 
-// one wavefront streams tile (I, J): P1 row sums into d1 (FP64), P2 (OFFDIAG) into its
-// FP64 column sums in LDS (p2), then the tile's P2 partial of r_J
+// one wavefront streams column half h of tile (I, J): P1 row sums into d1 (FP64), P2
+// (OFFDIAG) into its FP64 column sums in LDS (p2, the half's 64 columns), then the half's
+// P2 partial of r_J.  qj holds q_J of the half's 64 columns.
 template <int NRHS, bool OFFDIAG>
-__device__ __forceinline__ void hemv_tile(const f4v* __restrict__ kp, const float2* qj, double2* p2,
+__device__ __forceinline__ void hemv_half(const f4v* __restrict__ kp, const float2* qj, double2* p2,
                                           const float2 (&qi)[2][NRHS], double (&d1)[2][NRHS][2],
-                                          float2* __restrict__ r2part, int I, int J, int nbk, int L) {
-    const f4v* tp = kp + hemv_tile_index(I, J, nbk) * (2 * 64 * kWave) + L;
+                                          float2* __restrict__ r2part, int I, int J, int h, int nbk, int L) {
+    const f4v* tp = kp + (hemv_tile_index(I, J, nbk) * 2 + h) * (64 * kWave) + L;
     float a1[2][NRHS][2], a2[NRHS][2];
 #pragma unroll
     for (int e = 0; e < 2; ++e)
@@ -545,97 +546,91 @@ __device__ __forceinline__ void hemv_tile(const f4v* __restrict__ kp, const floa
 #pragma unroll
     for (int r = 0; r < NRHS; ++r) a2[r][0] = a2[r][1] = 0.0f;
 #pragma unroll 1
-    for (int h = 0; h < 2; ++h) {
-#pragma unroll 1
-        for (int sf = 0; sf < 64; sf += kHemvFlush) {
+    for (int sf = 0; sf < 64; sf += kHemvFlush) {
 #pragma unroll
-            for (int s0 = sf; s0 < sf + kHemvFlush; s0 += kHemvUnroll) {
-                f4v kv[kHemvUnroll];
+        for (int s0 = sf; s0 < sf + kHemvFlush; s0 += kHemvUnroll) {
+            f4v kv[kHemvUnroll];
 #pragma unroll
-                for (int u = 0; u < kHemvUnroll; ++u)
-                    kv[u] = __builtin_nontemporal_load(tp + (int64_t)((h * 64 + s0 + u) * kWave));
+            for (int u = 0; u < kHemvUnroll; ++u) kv[u] = __builtin_nontemporal_load(tp + (int64_t)((s0 + u) * kWave));
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < kHemvUnroll; ++u) {
+                // keep each step's LDS reads next to its arithmetic
                 __builtin_amdgcn_sched_barrier(0);
+                const int c = (L + s0 + u) & 63;
+                const float k0r = kv[u].x, k0i = kv[u].y, k1r = kv[u].z, k1i = kv[u].w;
 #pragma unroll
-                for (int u = 0; u < kHemvUnroll; ++u) {
-                    // keep each step's LDS reads next to its arithmetic
-                    __builtin_amdgcn_sched_barrier(0);
-                    const int s = s0 + u;
-                    const int c = 64 * h + ((L + s) & 63);
-                    const float k0r = kv[u].x, k0i = kv[u].y, k1r = kv[u].z, k1i = kv[u].w;
+                for (int r = 0; r < NRHS; ++r) {
+                    const float2 q = qj[r * 64 + c];
+                    // P1: row L and row 64 + L times q_J[c]
+                    a1[0][r][0] = fmaf(k0r, q.x, a1[0][r][0]);
+                    a1[0][r][0] = fmaf(-k0i, q.y, a1[0][r][0]);
+                    a1[0][r][1] = fmaf(k0r, q.y, a1[0][r][1]);
+                    a1[0][r][1] = fmaf(k0i, q.x, a1[0][r][1]);
+                    a1[1][r][0] = fmaf(k1r, q.x, a1[1][r][0]);
+                    a1[1][r][0] = fmaf(-k1i, q.y, a1[1][r][0]);
+                    a1[1][r][1] = fmaf(k1r, q.y, a1[1][r][1]);
+                    a1[1][r][1] = fmaf(k1i, q.x, a1[1][r][1]);
+                }
+                if (OFFDIAG) {
+                    // P2: column c gets conj(K[L][c]) q_I[L] + conj(K[64 + L][c]) q_I[64 + L]
 #pragma unroll
                     for (int r = 0; r < NRHS; ++r) {
-                        const float2 q = qj[r * kHemvTile + c];
-                        // P1: row L and row 64 + L times q_J[c]
-                        a1[0][r][0] = fmaf(k0r, q.x, a1[0][r][0]);
-                        a1[0][r][0] = fmaf(-k0i, q.y, a1[0][r][0]);
-                        a1[0][r][1] = fmaf(k0r, q.y, a1[0][r][1]);
-                        a1[0][r][1] = fmaf(k0i, q.x, a1[0][r][1]);
-                        a1[1][r][0] = fmaf(k1r, q.x, a1[1][r][0]);
-                        a1[1][r][0] = fmaf(-k1i, q.y, a1[1][r][0]);
-                        a1[1][r][1] = fmaf(k1r, q.y, a1[1][r][1]);
-                        a1[1][r][1] = fmaf(k1i, q.x, a1[1][r][1]);
+                        float re = a2[r][0], im = a2[r][1];
+                        re = fmaf(k0r, qi[0][r].x, re);
+                        re = fmaf(k0i, qi[0][r].y, re);
+                        re = fmaf(k1r, qi[1][r].x, re);
+                        re = fmaf(k1i, qi[1][r].y, re);
+                        im = fmaf(k0r, qi[0][r].y, im);
+                        im = fmaf(-k0i, qi[0][r].x, im);
+                        im = fmaf(k1r, qi[1][r].y, im);
+                        im = fmaf(-k1i, qi[1][r].x, im);
+                        // the partial moves on with its column: lane L now holds column
+                        // (L + s + 1) mod 64 of the half
+                        a2[r][0] = wave_rol1(re);
+                        a2[r][1] = wave_rol1(im);
                     }
-                    if (OFFDIAG) {
-                        // P2: column c gets conj(K[L][c]) q_I[L] + conj(K[64 + L][c]) q_I[64 + L]
-#pragma unroll
-                        for (int r = 0; r < NRHS; ++r) {
-                            float re = a2[r][0], im = a2[r][1];
-                            re = fmaf(k0r, qi[0][r].x, re);
-                            re = fmaf(k0i, qi[0][r].y, re);
-                            re = fmaf(k1r, qi[1][r].x, re);
-                            re = fmaf(k1i, qi[1][r].y, re);
-                            im = fmaf(k0r, qi[0][r].y, im);
-                            im = fmaf(-k0i, qi[0][r].x, im);
-                            im = fmaf(k1r, qi[1][r].y, im);
-                            im = fmaf(-k1i, qi[1][r].x, im);
-                            // the partial moves on with its column: lane L now holds
-                            // column 64 h + (L + s + 1) mod 64
-                            a2[r][0] = wave_rol1(re);
-                            a2[r][1] = wave_rol1(im);
-                        }
-                    }
-                }
-            }
-            // end of a run: FP32 sums into FP64
-#pragma unroll
-            for (int e = 0; e < 2; ++e)
-#pragma unroll
-                for (int r = 0; r < NRHS; ++r) {
-                    d1[e][r][0] += (double)a1[e][r][0];
-                    d1[e][r][1] += (double)a1[e][r][1];
-                    a1[e][r][0] = a1[e][r][1] = 0.0f;
-                }
-            if (OFFDIAG) {
-                // the P2 sums of a column are read and written by different lanes at
-                // different runs: keep this wavefront's LDS accesses in order
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                const int cn = 64 * h + ((L + sf + kHemvFlush) & 63);
-#pragma unroll
-                for (int r = 0; r < NRHS; ++r) {
-                    double2 v = p2[r * kHemvTile + cn];
-                    v.x += (double)a2[r][0];
-                    v.y += (double)a2[r][1];
-                    p2[r * kHemvTile + cn] = v;
-                    a2[r][0] = a2[r][1] = 0.0f;
                 }
             }
         }
-    }
-    // P2 partial of r_J: this tile's 128 columns (the last flush of each half left
-    // column 64 h + L on lane L)
-    if (OFFDIAG) {
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        float2* out = r2part + hemv_tile_index(I, J, nbk) * kHemvTile * NRHS;
+        // end of a run: FP32 sums into FP64
 #pragma unroll
         for (int e = 0; e < 2; ++e)
 #pragma unroll
             for (int r = 0; r < NRHS; ++r) {
-                const double2 v = p2[r * kHemvTile + 64 * e + L];
-                out[(64 * e + L) * NRHS + r] = make_float2((float)v.x, (float)v.y);
+                d1[e][r][0] += (double)a1[e][r][0];
+                d1[e][r][1] += (double)a1[e][r][1];
+                a1[e][r][0] = a1[e][r][1] = 0.0f;
             }
+        if (OFFDIAG) {
+            // the P2 sums of a column are read and written by different lanes at different
+            // runs: keep this wavefront's LDS accesses in order
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            const int cn = (L + sf + kHemvFlush) & 63;
+#pragma unroll
+            for (int r = 0; r < NRHS; ++r) {
+                double2 v = p2[r * 64 + cn];
+                v.x += (double)a2[r][0];
+                v.y += (double)a2[r][1];
+                p2[r * 64 + cn] = v;
+                a2[r][0] = a2[r][1] = 0.0f;
+            }
+        }
+    }
+    // P2 partial of r_J for the half's 64 columns (the last run left column L on lane L)
+    if (OFFDIAG) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        float2* out = r2part + hemv_tile_index(I, J, nbk) * kHemvTile * NRHS;
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) {
+            const double2 v = p2[r * 64 + L];
+            out[(64 * h + L) * NRHS + r] = make_float2((float)v.x, (float)v.y);
+        }
     }
 }
 
+// Block = 4 wavefronts on 2 consecutive tiles of tile row I (wavefront w: tile J =
+// I + 2 g + w / 2, column half w % 2).
 template <int NRHS>
 __global__ __launch_bounds__(256, 4) void k_hemv(const f4v* __restrict__ kp, const double2* __restrict__ qbar,
                                                  const int* __restrict__ table, float2* __restrict__ r1part,
@@ -645,13 +640,15 @@ __global__ __launch_bounds__(256, 4) void k_hemv(const f4v* __restrict__ kp, con
     const int L = threadIdx.x % kWave;
     const int code = table[blockIdx.x];
     const int I = code & 0xffff, g = code >> 16;
-    const int J = I + 4 * g + wave;
+    const int J = I + 2 * g + (wave >> 1);
+    const int h = wave & 1;
     const bool active = J < nbk;       // wavefront-uniform
     const bool offdiag = J != I;
-    // LDS: q_J of each wavefront [4][NRHS][128] (float2), then the FP64 P2 sums [4][NRHS][128]
-    float2* qj = reinterpret_cast<float2*>(hsm) + wave * NRHS * kHemvTile;
-    double2* p2 = hsm + 4 * NRHS * kHemvTile / 2 + wave * NRHS * kHemvTile;
-    // q_I of this lane's two rows (FP32) and q_J of the tile's columns in LDS
+    // LDS: q_J of each wavefront's 64 columns [4][NRHS][64] (float2), then the FP64 P2 sums
+    // [4][NRHS][64]; at the end the P1 sums [4][128][NRHS] (double2) over both
+    float2* qj = reinterpret_cast<float2*>(hsm) + wave * NRHS * 64;
+    double2* p2 = hsm + 4 * NRHS * 64 / 2 + wave * NRHS * 64;
+    // q_I of this lane's two rows (FP32) and q_J of the half's columns in LDS
     float2 qi[2][NRHS];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -663,15 +660,12 @@ __global__ __launch_bounds__(256, 4) void k_hemv(const f4v* __restrict__ kp, con
         }
     }
     if (active) {
+        const int col = J * kHemvTile + 64 * h + L;
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int col = J * kHemvTile + 64 * e + L;
-#pragma unroll
-            for (int r = 0; r < NRHS; ++r) {
-                const double2 q = col < Nc ? qbar[(int64_t)col * NRHS + r] : make_double2(0.0, 0.0);
-                qj[r * kHemvTile + 64 * e + L] = make_float2((float)q.x, (float)q.y);
-                p2[r * kHemvTile + 64 * e + L] = make_double2(0.0, 0.0);
-            }
+        for (int r = 0; r < NRHS; ++r) {
+            const double2 q = col < Nc ? qbar[(int64_t)col * NRHS + r] : make_double2(0.0, 0.0);
+            qj[r * 64 + L] = make_float2((float)q.x, (float)q.y);
+            p2[r * 64 + L] = make_double2(0.0, 0.0);
         }
     }
     __syncthreads();
@@ -682,13 +676,13 @@ __global__ __launch_bounds__(256, 4) void k_hemv(const f4v* __restrict__ kp, con
         for (int r = 0; r < NRHS; ++r) d1[e][r][0] = d1[e][r][1] = 0.0;
     if (active) {
         if (offdiag)
-            hemv_tile<NRHS, true>(kp, qj, p2, qi, d1, r2part, I, J, nbk, L);
+            hemv_half<NRHS, true>(kp, qj, p2, qi, d1, r2part, I, J, h, nbk, L);
         else
-            hemv_tile<NRHS, false>(kp, qj, p2, qi, d1, r2part, I, J, nbk, L);
+            hemv_half<NRHS, false>(kp, qj, p2, qi, d1, r2part, I, J, h, nbk, L);
     }
     // P1 partial of r_I: the 4 wavefronts' row sums added in LDS in a fixed order
     __syncthreads();
-    double2* red = hsm + 4 * NRHS * kHemvTile / 2;   // [4][128][NRHS], over the P2 sums
+    double2* red = hsm;   // [4][128][NRHS]
 #pragma unroll
     for (int e = 0; e < 2; ++e)
 #pragma unroll
@@ -708,34 +702,43 @@ __global__ __launch_bounds__(256, 4) void k_hemv(const f4v* __restrict__ kp, con
 }
 
 // r[i][rhs] = sum of the P1 partials of tile row b = i / 128 (its blocks in order), then of
-// the P2 partials of tiles (I, b), I < b, in order of I
+// the P2 partials of tiles (I, b), I < b, in order of I.  Eight lanes per output: lane k
+// adds partials k, k + 8, ... (FP64), then the eight sums are added in a fixed butterfly.
+constexpr int kHemvRedLanes = 8;
+
 template <int NRHS>
 __global__ __launch_bounds__(256) void k_hemv_reduce(const float2* __restrict__ r1part,
                                                      const float2* __restrict__ r2part, const int* __restrict__ band0,
                                                      double2* __restrict__ rout, int Nc, int nbk) {
-    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= (int64_t)Nc * NRHS) return;
-    const int i = (int)(o / NRHS), r = (int)(o % NRHS);
+    const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kHemvRedLanes;
+    const int k = threadIdx.x % kHemvRedLanes;
+    const int64_t oc = min(o, (int64_t)Nc * NRHS - 1);   // lanes past the end: same work, no store
+    const int i = (int)(oc / NRHS), r = (int)(oc % NRHS);
     const int b = i / kHemvTile, w = i % kHemvTile;
     const int p0 = band0[b], np1 = band0[b + 1] - p0;
     const int n = np1 + b;   // P1 partials, then P2 partials of tiles (0, b) .. (b - 1, b)
     double re = 0.0, im = 0.0;
-    for (int t0 = 0; t0 < n; t0 += 8) {
-        float2 v[8];
+    for (int t0 = k; t0 < n; t0 += 4 * kHemvRedLanes) {
+        float2 v[4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int t = min(t0 + u, n - 1);
+        for (int u = 0; u < 4; ++u) {
+            const int t = min(t0 + u * kHemvRedLanes, n - 1);
             const int64_t src = t < np1 ? (int64_t)(p0 + t) : hemv_tile_index(t - np1, b, nbk);
             v[u] = (t < np1 ? r1part : r2part)[(src * kHemvTile + w) * NRHS + r];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (t0 + u < n) {
+        for (int u = 0; u < 4; ++u)
+            if (t0 + u * kHemvRedLanes < n) {
                 re += (double)v[u].x;
                 im += (double)v[u].y;
             }
     }
-    rout[o] = make_double2(re, im);
+#pragma unroll
+    for (int off = 1; off < kHemvRedLanes; off <<= 1) {
+        re += __shfl_xor(re, off, kWave);
+        im += __shfl_xor(im, off, kWave);
+    }
+    if (k == 0 && o < (int64_t)Nc * NRHS) rout[o] = make_double2(re, im);
 }
 
 HemvShape hemv_shape(int64_t Nc) {
@@ -743,7 +746,7 @@ HemvShape hemv_shape(int64_t Nc) {
     h.nbk = (int)((Nc + kHemvTile - 1) / kHemvTile);
     h.tiles = (int64_t)h.nbk * (h.nbk + 1) / 2;
     int64_t b = 0;
-    for (int I = 0; I < h.nbk; ++I) b += (h.nbk - I + 3) / 4;
+    for (int I = 0; I < h.nbk; ++I) b += (h.nbk - I + 1) / 2;
     h.blocks = b;
     h.tile_bytes = (size_t)kHemvTile * kHemvTile * sizeof(float2);
     return h;
@@ -768,14 +771,17 @@ static hipError_t hemv_t(Plan& p, hipStream_t s) {
     const int* tab = reinterpret_cast<const int*>(p.ws + p.L.htab);
     float2* r1 = reinterpret_cast<float2*>(p.ws + p.L.hpart);
     float2* r2 = r1 + (size_t)h.blocks * kHemvTile * NRHS;
-    const size_t lds = (size_t)4 * NRHS * kHemvTile * (sizeof(float2) + sizeof(double2));
+    // q_J and P2 sums of 4 wavefronts x 64 columns, or the P1 sums of 4 x 128 rows
+    const size_t lds = std::max((size_t)4 * NRHS * 64 * (sizeof(float2) + sizeof(double2)),
+                                (size_t)4 * kHemvTile * NRHS * sizeof(double2));
     hipLaunchKernelGGL((k_hemv<NRHS>), dim3((unsigned)h.blocks), dim3(kBlock), lds, s,
                        reinterpret_cast<const f4v*>(p.ws + p.L.kp), reinterpret_cast<const double2*>(p.ws + p.L.qbar),
                        tab, r1, r2, (int)g.Nc, h.nbk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t n_out = g.Nc * NRHS;
-    hipLaunchKernelGGL((k_hemv_reduce<NRHS>), dim3((unsigned)((n_out + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, r1,
+    const int64_t n_thr = n_out * kHemvRedLanes;
+    hipLaunchKernelGGL((k_hemv_reduce<NRHS>), dim3((unsigned)((n_thr + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, r1,
                        r2, tab + h.blocks, reinterpret_cast<double2*>(p.ws + p.L.rvec), (int)g.Nc, h.nbk);
     return hipGetLastError();
 }

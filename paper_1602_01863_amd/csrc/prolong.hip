@@ -18,6 +18,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "bse_device.hpp"
 #include "bse_plan.hpp"
 
@@ -158,9 +160,11 @@ __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, V2, NV,
     const int ndiv3 = n_div * n_div * n_div;
     const int blk = NE * ndiv3;                // entries of one (cell, corner) block
     const int blku = (blk + U::P - 1) / U::P;  // its 16-byte units (blocks start 16-byte aligned)
+    using IT = typename Inner<M2>::t;   // precision of the per-(subpoint, corner) contractions
+    using RS = typename std::conditional<sizeof(IT) == 4, float2, double2>::type;
     Rw* dbuf0 = reinterpret_cast<Rw*>(lds2);
     Rw* dbuf1 = dbuf0 + blku;
-    double2* rs = lds2 + 2 * blku;
+    RS* rs = reinterpret_cast<RS*>(lds2 + 2 * blku);   // r of the 8 corners, in IT
     const int cell = blockIdx.x;
     const int t = threadIdx.x;
     const int wave = t / kWave;
@@ -191,7 +195,12 @@ __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, V2, NV,
             ftab[(i / ndiv3) * kWave + i % ndiv3] = prefactor(i % ndiv3, i / ndiv3, n_div, neighbours);
 #pragma unroll
         for (int q = 0; q < 2; ++q)
-            if (t + q * NT < 8 * per) rs[t + q * NT] = rv[q];
+            if (t + q * NT < 8 * per) {
+                RS v;
+                v.x = (decltype(v.x))rv[q].x;
+                v.y = (decltype(v.y))rv[q].y;
+                rs[t + q * NT] = v;
+            }
 #pragma unroll
         for (int q = 0; q < PFU; ++q)
             if (t + q * NT < blku) dbuf0[t + q * NT] = pf[q];
@@ -212,9 +221,50 @@ __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, V2, NV,
         }
         __syncthreads();
         const M2* cur = reinterpret_cast<const M2*>((z & 1) ? dbuf1 : dbuf0);
-        if (active) {
+        if (active && sizeof(IT) == 4) {
+            // FP32 overlaps: tt[q][n1] = sum_{n2} r[n1][n2] conj(Dc[c(q)][n2]) and
+            // Y[v][q] = f sum_{n1} Dv[v][n1] tt[q][n1] in FP32, Y added into the FP64 sum
+            // over the corners
+            const IT f = (IT)ftab[z * kWave + lane];
+            const RS* rz = rs + z * per + rhs;
+            cplx<IT> tt[NCH][NV];
+#pragma unroll
+            for (int q = 0; q < NCH; ++q)
+#pragma unroll
+                for (int n1 = 0; n1 < NV; ++n1) tt[q][n1] = czero<IT>();
+#pragma unroll
+            for (int n2 = 0; n2 < NC; ++n2) {
+                __builtin_amdgcn_sched_barrier(0);
+                cplx<IT> rc[NV];
+#pragma unroll
+                for (int n1 = 0; n1 < NV; ++n1) rc[n1] = cl<IT>(rz[(n1 * NC + n2) * NR]);
+#pragma unroll
+                for (int q = 0; q < NCH; ++q) {
+                    const int c = h * NCH + q;
+                    if (c >= NC) break;
+                    const cplx<IT> dc = cl<IT>(cur[(NV * NV + c * NC + n2) * ndiv3 + lane]);
+#pragma unroll
+                    for (int n1 = 0; n1 < NV; ++n1) cmac_jc(tt[q][n1], rc[n1], dc);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                cplx<IT> dvv[NV];
+#pragma unroll
+                for (int n1 = 0; n1 < NV; ++n1) dvv[n1] = cl<IT>(cur[(v * NV + n1) * ndiv3 + lane]);
+#pragma unroll
+                for (int q = 0; q < NCH; ++q) {
+                    cplx<IT> Y = czero<IT>();
+#pragma unroll
+                    for (int n1 = 0; n1 < NV; ++n1) cmac(Y, dvv[n1], tt[q][n1]);
+                    Y.re *= f;
+                    Y.im *= f;
+                    cadd_to(acc[v][q], Y);
+                }
+            }
+        } else if (active) {
             const double f = ftab[z * kWave + lane];
-            const double2* rz = rs + z * per + rhs;
+            const RS* rz = rs + z * per + rhs;
             M2 dv[NV * NV];   // storage precision, widened at use
 #pragma unroll
             for (int e = 0; e < NV * NV; ++e) dv[e] = cur[e * ndiv3 + lane];
@@ -230,7 +280,7 @@ __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, V2, NV,
                 cd rc[NV];
 #pragma unroll
                 for (int n1 = 0; n1 < NV; ++n1) {
-                    const double2 r = rz[(n1 * NC + n2) * NR];
+                    const RS r = rz[(n1 * NC + n2) * NR];
                     rc[n1] = cmake(r.x, r.y);
                 }
 #pragma unroll

@@ -273,6 +273,7 @@ __global__ __launch_bounds__(256, (NR == 1 && sizeof(M2) == 8 && NV * NC <= 18) 
     using U = Unit16<M2>;
     using R = typename U::t;
     constexpr int NU = (KL + U::P - 1) / U::P;  // 16-byte loads per lane and tile
+    using IT = typename Inner<M2>::t;           // precision of the per-subpoint contractions
     extern __shared__ double2 lds_raw[];
     __shared__ double sred[2 * NR][NW];
     const int ndiv3 = n_div * n_div * n_div;
@@ -490,26 +491,55 @@ __global__ __launch_bounds__(256, (NR == 1 && sizeof(M2) == 8 && NV * NC <= 18) 
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) {
             const V2* xrow = xs + rr * xstride + (4 * s + j) * NP;
-            // for each v: T[q] = sum_c x[v][c] Dc[c][n2(q)] over this lane's half of n2,
-            // then acc[n3][q] += conj(f Dv[v][n3]) T[q]
+            if constexpr (sizeof(IT) == 8) {
+                // FP64 overlaps: for each v, T[q] = sum_c x[v][c] Dc[c][n2(q)] over this
+                // lane's half of n2, then acc[n3][q] += conj(f Dv[v][n3]) T[q]
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                cd T[NCH];
+                for (int v = 0; v < NV; ++v) {
+                    cd T[NCH];
 #pragma unroll
-                for (int q = 0; q < NCH; ++q) T[q] = cmake(0.0, 0.0);
+                    for (int q = 0; q < NCH; ++q) T[q] = cmake(0.0, 0.0);
 #pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const cd xc = cv(xrow[v * NC + c]);
+                    for (int c = 0; c < NC; ++c) {
+                        const cd xc = cv(xrow[v * NC + c]);
 #pragma unroll
-                    for (int q = 0; q < NCH; ++q) cfma(T[q], xc, cv(entry(NDV + c * NCH + q)));
+                        for (int q = 0; q < NCH; ++q) cfma(T[q], xc, cv(entry(NDV + c * NCH + q)));
+                    }
+#pragma unroll
+                    for (int n3 = 0; n3 < NV; ++n3) {
+                        const cd dvv = cv(dv[v * NV + n3]);
+#pragma unroll
+                        for (int q = 0; q < NCH; ++q) cfma_cj(acc[rr][n3][q], dvv, T[q]);
+                    }
                 }
+                continue;
+            }
+            // FP32 overlaps: T[v][q] = sum_c x[v][c] Dc[c][n2(q)] over this lane's half of
+            // n2, then Y[n3][q] = sum_v conj(f Dv[v][n3]) T[v][q], both in FP32; Y is added
+            // into the FP64 sum over the cell's subpoints
+            cplx<IT> T[NV][NCH];
 #pragma unroll
-                for (int n3 = 0; n3 < NV; ++n3) {
-                    const cd dvv = cv(dv[v * NV + n3]);
+            for (int v = 0; v < NV; ++v)
 #pragma unroll
-                    for (int q = 0; q < NCH; ++q) cfma_cj(acc[rr][n3][q], dvv, T[q]);
+                for (int q = 0; q < NCH; ++q) T[v][q] = czero<IT>();
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const cplx<IT> xc = cl<IT>(xrow[v * NC + c]);
+#pragma unroll
+                    for (int q = 0; q < NCH; ++q) cmac(T[v][q], xc, cl<IT>(entry(NDV + c * NCH + q)));
                 }
             }
+#pragma unroll
+            for (int n3 = 0; n3 < NV; ++n3)
+#pragma unroll
+                for (int q = 0; q < NCH; ++q) {
+                    cplx<IT> Y = czero<IT>();
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) cmac_cj(Y, cl<IT>(dv[v * NV + n3]), T[v][q]);
+                    cadd_to(acc[rr][n3][q], Y);
+                }
         }
     }
     // sum the 4 subpoint columns of each (corner, half), then the wavefronts

@@ -42,6 +42,15 @@ def abs_operator(op: O.InterpOperator) -> O.InterpOperator:
 # the prolong carries that to |C|^H |K| |C| |x| on top of the 10 units of storage rounding.
 PACKED_PRODUCT_UNITS = 66
 
+# With FP32 overlaps the restrict and the prolong form their per-(subpoint, corner)
+# contractions in FP32 and add the results in FP64.  Restrict: T = sum over 6 c of
+# x Dc (12 FMAs per component, 12 units), then Y = sum over 3 v of conj(f Dv) T (6 FMAs,
+# 6 units), plus the rounding of an FP64 vector entry to FP32 (1 unit): 19 units of
+# sum |f Dv| |x| |Dc|.  Prolong: r rounded to FP32 (1), the 6-term sum over n2 (12), the
+# 3-term sum over n1 (6) and the product with f (1): 20 units of sum f |Dv| |r| |Dc|.
+# Both reach the output through |C|^H |K| |C| |x|: 39 units on the kernel terms.
+FP32_INNER_UNITS = 19 + 20
+
 
 def product_bound(op: O.InterpOperator, x, unit: float, factors: int = 10, kernel_factors=None):
     """Componentwise bound on |y_gpu - y| for storage rounding of unit `unit`.
@@ -62,6 +71,7 @@ def product_bound(op: O.InterpOperator, x, unit: float, factors: int = 10, kerne
 
 
 def fp32_kernel_factors(packed: bool) -> int:
-    """Units of the kernel terms for the FP32 coarse kernel: storage rounding (10), plus the
-    packed product's own arithmetic when it runs (form 0)."""
-    return 10 + (PACKED_PRODUCT_UNITS if packed else 0)
+    """Units of the kernel terms with FP32 overlaps and coarse kernel: storage rounding
+    (10), the restrict's and prolong's FP32 contractions, and the packed coarse product's
+    own arithmetic when it runs (form 0)."""
+    return 10 + FP32_INNER_UNITS + (PACKED_PRODUCT_UNITS if packed else 0)

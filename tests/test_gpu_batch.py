@@ -100,18 +100,29 @@ def _window(ref, other, tol):
     return min(out)
 
 
+def _fp32_storage(cfg):
+    """The oracle's operator with its overlaps and K_c rounded to complex64 (the storage
+    of the FP32 forms), still applied in FP64."""
+    bs, Dv, Dc, f, Kc, delta = oracle_parts(cfg)
+    c64 = lambda a: a.astype(np.complex64).astype(np.complex128)
+    return O.InterpOperator(c64(Dv), c64(Dc), f, c64(Kc), delta, cfg.n_coarse, cfg.n_div, cfg.nv, cfg.nc)
+
+
 def test_batch_chains_match_the_oracle(bse):
     """Every member's batched chains (Eqs. ai-ci; 200 steps, the batching workload's
     length) against the oracle's FP64 chains of the same Hamiltonian: the ±delta
     displaced member, the FP32-vector and FP64-vector members and the BF16 member.
 
     * head: the oracle against its own rounding-perturbed run (the FP64 member against
-      a one-ulp change of the diagonal, the FP32-storage members against complex64
-      storage of every vector) stays at the rounding floor and then departs, growing
-      17-50x per step, once converged states re-enter.  Two steps before it first
-      departs by more than the tolerance, the batched coefficients agree with the
-      oracle to 1e-10 (FP64) or 1e-6 (FP32); that window must hold at least 10
-      coefficients.  The BF16 member: a_1 within the
+      a one-ulp change of the diagonal; the FP32 members with their overlaps and K_c
+      rounded to complex64, and the vectors too where they are stored in FP32) stays at
+      the rounding floor and then departs, growing 17-50x per step, once converged
+      states re-enter.  Two steps before the emulated departure the batched
+      coefficients agree with the oracle to 1e-10 (FP64) or, for the FP32 forms, 1e-5:
+      their FP32 arithmetic (restrict, prolong, packed coarse product) perturbs each
+      matvec by up to 115 FP32 units of the sum of |terms| of its kernel part, a few
+      times the storage rounding (about 3e-6 of a_1 here); that window must hold at
+      least 10 coefficients.  The BF16 member: a_1 within the
       format bound 2^-8 <|qbar_1|, |K_c| |qbar_1|> (K_c entries rounded to 8 significant
       bits, block scales are powers of two).
     * eps2 at eta = 0.5 eV, where 200 steps have converged (the oracle's FP32-storage
@@ -139,15 +150,16 @@ def test_batch_chains_match_the_oracle(bse):
             assert np.all(np.abs(got["a"][:, 0] - ref["a"][:, 0]) <= bound + 1e-12), cfg.name
             tol_eps = 1e-3
         else:
-            tol = 1e-10 if dt == "f64" else 1e-6
+            tol = 1e-10 if dt == "f64" else 1e-5
             if dt == "f64":
                 op2 = oracle_operator(cfg)
                 op2.delta = np.nextafter(op.delta, np.inf)
                 pert = O.haydock(op2.apply, P, 40)
             else:
-                pert = O.haydock(op.apply, P, 40, round_dtype=np.complex64)
+                pert = O.haydock(_fp32_storage(cfg).apply, P, 40,
+                                 round_dtype=np.complex64 if dt == "f32" else None)
             head = dict(a=ref["a"][:, :40], b=ref["b"][:, :41])
-            w = _window(head, pert, tol) - 2
+            w = _window(head, pert, 1e-10 if dt == "f64" else 1e-6) - 2
             assert w >= 10, (cfg.name, w)
             for r in range(P.shape[0]):
                 assert np.all(np.abs(got["a"][r, :w] - ref["a"][r, :w]) <= tol * np.abs(ref["a"][r, :w])), (cfg.name, r)
@@ -176,9 +188,9 @@ def test_batch_workload_shapes_against_the_oracle(bse, cfg):
       sum of |terms| (storage rounding, and the packed coarse product's arithmetic on the
       kernel terms) and 2e-6 in relative L2;
     * the member's chains run in a batch (200 steps, 3 polarisations) against the
-      oracle's FP64 chain head to 1e-6, up to two steps before the oracle's
-      complex64-storage emulation first departs from FP64 by more than 1e-6 (at
-      least 8 coefficients)."""
+      oracle's FP64 chain head to 1e-5, up to two steps before the oracle with every
+      stored array in complex64 (overlaps, K_c, vectors) first departs from FP64 by more
+      than 1e-6 (at least 8 coefficients; the tolerance as in the test above)."""
     bs = bands(cfg)
     prob = bse.problem_from_bands(bs, cfg, dtype="f32", max_rhs=3)
     cells = np.array([0, cfg.nk_coarse // 3, cfg.nk_coarse - 1])
@@ -192,12 +204,12 @@ def test_batch_workload_shapes_against_the_oracle(bse, cfg):
     op = oracle_operator(cfg)
     n = 16
     ref = O.haydock(op.apply, P, n)
-    emu = O.haydock(op.apply, P, n, round_dtype=np.complex64)
+    emu = O.haydock(_fp32_storage(cfg).apply, P, n, round_dtype=np.complex64)
     w = _window(ref, emu, 1e-6) - 2
     assert w >= 8, w
     np.testing.assert_allclose(got["pnorm2"], ref["pnorm2"], rtol=1e-12)
     for r in range(3):
-        assert np.all(np.abs(got["a"][r, :w] - ref["a"][r, :w]) <= 1e-6 * np.abs(ref["a"][r, :w])), r
-        assert np.all(np.abs(got["b"][r, 1:w + 1] - ref["b"][r, 1:w + 1]) <= 1e-6 * np.abs(ref["b"][r, 1:w + 1])), r
+        assert np.all(np.abs(got["a"][r, :w] - ref["a"][r, :w]) <= 1e-5 * np.abs(ref["a"][r, :w])), r
+        assert np.all(np.abs(got["b"][r, 1:w + 1] - ref["b"][r, 1:w + 1]) <= 1e-5 * np.abs(ref["b"][r, 1:w + 1])), r
     batch.close()
     prob.close()

@@ -60,6 +60,12 @@ def _read_chains(name):
     return dict(pnorm2=rows[:, 1], steps=rows[:, 2].astype(int), a=rows[:, 3:3 + m], b=rows[:, 3 + m:4 + 2 * m])
 
 
+def _departure(x, ref, tol):
+    """First coefficient index where any chain of x leaves ref by more than tol (relative)."""
+    bad = np.abs(x - ref) > tol * np.abs(ref)
+    return min(int(np.argmax(row)) if row.any() else row.size for row in bad)
+
+
 def test_c1_overlaps_sampled(c1, c1_oracle_pieces):
     bs, prob = c1
     Dv, Dc, _ = c1_oracle_pieces
@@ -146,7 +152,11 @@ def test_c1_haydock_against_oracle_chains(bse, dtype):
     * chain head: the oracle's complex64-storage emulation agrees with FP64 to
       1e-6 over the first 12 coefficients and departs by more than 1e-2 before the
       25th (tests/test_oracle_lanczos.py::test_chain_window_c1_fp32_storage):
-      rounding decides when converged states re-enter; the head is held to 1e-6.
+      rounding decides when converged states re-enter.  The library's FP32 arithmetic
+      (restrict, prolong and packed coarse product) perturbs every matvec by up to
+      115 FP32 units of the sum of |terms| of its kernel part (about 3e-6 of a_1), which
+      brings the departure up to two steps earlier; the head is held to 1e-5 relative
+      over the coefficients two steps before the emulated departure.
     * eps2 at broadenings where 300 steps have converged (0.2 and 0.3 eV; the
       emulation floor there is 2e-8): 1e-6.
     * eps2 at the workload's eta = 0.05 eV, where 300 steps have not converged and
@@ -162,9 +172,11 @@ def test_c1_haydock_against_oracle_chains(bse, dtype):
     assert np.all(ch["steps"].cpu().numpy() == CFG.steps)
     assert np.all(ch["status"].cpu().numpy() == bse.BSE_OK)
     np.testing.assert_allclose(ch["pnorm2"].cpu().numpy(), ref["pnorm2"], rtol=1e-12)
+    w = min(_departure(emu["a"], ref["a"], 1e-6), _departure(emu["b"][:, 1:], ref["b"][:, 1:], 1e-6)) - 2
+    assert w >= 10, w
     for r in range(3):
-        assert rel_l2(a[r, :12], ref["a"][r, :12]) < 1e-6
-        assert rel_l2(b[r, 1:13], ref["b"][r, 1:13]) < 1e-6
+        assert np.all(np.abs(a[r, :w] - ref["a"][r, :w]) <= 1e-5 * np.abs(ref["a"][r, :w])), r
+        assert np.all(np.abs(b[r, 1:w + 1] - ref["b"][r, 1:w + 1]) <= 1e-5 * np.abs(ref["b"][r, 1:w + 1])), r
     om = CFG.omega()
     pref = CFG.prefactor()
     for eta in (0.2, 0.3):

@@ -15,7 +15,7 @@ import oracle as O
 import tbinputs as ti
 
 from _cases import bands, rel_l2
-from _gpu import U32, fp32_kernel_factors
+from _gpu import FP32_INNER_UNITS, U32, fp32_kernel_factors
 
 pytestmark = pytest.mark.gpu
 
@@ -73,7 +73,7 @@ def test_c2_bf16_matvec_sampled_cells(c2):
     ref = delta[None] * xh + op.prolong(r)
     kern_abs = np.abs(aop.prolong(rabs))
     bound = 10 * U32 * (np.abs(delta)[None] * np.abs(xh) + kern_abs) \
-        + (U_BF16 + 4 * U_BF16 ** 2 + 64 * U32) * kern_abs
+        + (U_BF16 + 4 * U_BF16 ** 2 + (64 + FP32_INNER_UNITS) * U32) * kern_abs
     ndiv3 = CFG.n_div3
     for cell in SAMPLE_CELLS:
         sl = slice(cell * ndiv3 * np_, (cell + 1) * ndiv3 * np_)

@@ -15,7 +15,7 @@ import oracle as O
 import tbinputs as ti
 
 from _cases import bands, oracle_operator, rel_l2
-from _gpu import U32, abs_operator, product_bound
+from _gpu import FP32_INNER_UNITS, U32, abs_operator, product_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -55,12 +55,13 @@ def lowp_bound(op, x, dtype):
     - qbar as leading part + remainder in the format: relative u^2 (+ an absolute
       floor 2^-25 / 2^9 for FP16, which scales qbar by 2^9).
     - FP32 accumulation of the 64 products of one block: 64 u32 per |term|.
+    - the restrict's and prolong's FP32 contractions: FP32_INNER_UNITS u32.
     The kernel terms are bounded by |C|^H |K| |C| |x|.
     """
     aop = abs_operator(op)
     ax = np.abs(x)
     u = UNIT[dtype]
-    bound = product_bound(op, x, U32) + (u + 4 * u * u + 64 * U32) * np.abs(aop.apply_kernel(ax))
+    bound = product_bound(op, x, U32) + (u + 4 * u * u + (64 + FP32_INNER_UNITS) * U32) * np.abs(aop.apply_kernel(ax))
     if dtype == "f16":
         kmax = np.abs(op.Kc).max()
         colsum = np.abs(aop.restrict(ax)).sum(axis=1)                # 1^T |C||x| per rhs

@@ -11,7 +11,7 @@ import oracle as O
 import tbinputs as ti
 
 from _cases import bands, oracle_operator, oracle_parts, rel_l2
-from _gpu import PACKED_PRODUCT_UNITS, U32, U64, abs_operator
+from _gpu import FP32_INNER_UNITS, PACKED_PRODUCT_UNITS, U32, U64, abs_operator
 
 pytestmark = pytest.mark.gpu
 
@@ -126,8 +126,9 @@ def test_m3_matvec_fp64_matches_explicit_kernel(bse, weights):
 def test_m3_matvec_fp32_within_rounding_bound(bse, cfg, w):
     """FP32 storage: every output within 10 FP32 units of the sum of |terms| of the
     Method 1 product and of the band (each band term is a product of at most 8 stored
-    or rounded factors: x, four overlaps, a_c, the block, the output), plus the packed
-    coarse product's arithmetic on the Method 1 kernel terms."""
+    or rounded factors: x, four overlaps, a_c, the block, the output), plus the FP32
+    arithmetic of the restrict, prolong and packed coarse product on the Method 1 kernel
+    terms."""
     op, a, Sc, k2, s0 = _oracle_m3(cfg)
     off = O.m3.band_offsets(cfg.n_div, w)
     sd = O.m3.dense_shape(off, cfg.n_coarse, cfg.n_div, k2, s0)
@@ -139,7 +140,7 @@ def test_m3_matvec_fp32_within_rounding_bound(bse, cfg, w):
     aop = abs_operator(op)
     ablocks = O.m3.band_blocks(aop, np.abs(a).astype(complex), Sc, off, sd, absolute=True)
     bound = 10 * U32 * np.abs(O.m3.apply(aop, ablocks, off, np.abs(x))) \
-        + PACKED_PRODUCT_UNITS * U32 * np.abs(aop.apply_kernel(np.abs(x)))
+        + (FP32_INNER_UNITS + PACKED_PRODUCT_UNITS) * U32 * np.abs(aop.apply_kernel(np.abs(x)))
     prob = bse.problem_from_bands(bands(cfg), cfg, dtype="f32", max_rhs=cfg.n_pol)
     prob.set_m3(w)
     y = prob.matvec(x).cpu().numpy().astype(np.complex128)
