@@ -217,6 +217,30 @@ bse_status bse_haydock_run(bse_plan* plan, const double* P, int32_t n_rhs, int32
                            int32_t* status, hipStream_t stream);
 
 /*
+ * Haydock chains run until their spectrum has converged (Sec. 2 after Eq. fraccont: the
+ * recursion stops when eps_M(omega) is converged at each frequency).  The chains advance
+ * as in bse_haydock_run; after every check_every steps a kernel evaluates eps_M of each
+ * chain on the omega grid (Eq. fraccont, z = omega + i eta) and compares eps2 = Im eps_M
+ * with the previous check: a chain stops (status BSE_OK, steps_done = its steps) once
+ * max_omega |eps2 - eps2_previous| <= tol max_omega |eps2| (the paper gives 1% without a
+ * denominator; here the change is measured against the spectrum's largest value), or
+ * after max_steps steps.  Breakdown and zero start end a chain as in bse_haydock_run.
+ *   P, a, b, pnorm2, steps_done, status   as bse_haydock_run with n_steps = max_steps
+ *                                          (lda = max_steps, ldb = max_steps + 1)
+ *   omega      device FP64 [n_omega]
+ *   eps_re, eps_im  device FP64 [n_rhs][n_omega]: eps_M of the last check (the converged
+ *              spectrum), also the previous spectrum between checks
+ * The host reads one flag per check while the next check_every steps run, so at most one
+ * chunk past the convergence of the last chain is enqueued (it leaves the stopped chains
+ * unchanged).  The call returns after the stream has finished the run.
+ */
+bse_status bse_haydock_converge(bse_plan* plan, const double* P, int32_t n_rhs, int32_t max_steps,
+                                int32_t check_every, double prefactor, const double* omega,
+                                int32_t n_omega, double eta, double tol, double* a, double* b,
+                                double* pnorm2, int32_t* steps_done, int32_t* status, double* eps_re,
+                                double* eps_im, hipStream_t stream);
+
+/*
  * eps_M(omega) = 1 - prefactor ||P||^2 / (z - a_1 - b_2^2 / (z - a_2 - ...)),
  * z = omega + i eta, truncated after a_m with m = steps[chain] (Eq. fraccont).
  * All pointers device; chains are stored with leading dimensions lda (a) and

@@ -38,7 +38,7 @@ EXPORTED = [
     "bse_version", "bse_last_error", "bse_workspace_bytes", "bse_coarse_kernel_bytes",
     "bse_overlaps_bytes", "bse_build_overlaps", "bse_build_transition_energies",
     "bse_build_coarse_kernel", "bse_plan_create", "bse_plan_destroy", "bse_interp_matvec",
-    "bse_haydock_run", "bse_continued_fraction", "bse_plan_set_timing", "bse_plan_get_timing",
+    "bse_haydock_run", "bse_haydock_converge", "bse_continued_fraction", "bse_plan_set_timing", "bse_plan_get_timing",
     "bse_plan_set_gemv_splits", "bse_plan_set_coarse_product", "bse_plan_set_restrict_group", "bse_batch_create", "bse_batch_launch",
     "bse_batch_destroy", "bse_dense_forward", "bse_dense_backward", "bse_dense_backward_noalloc", "bse_mse_loss", "bse_adam_step",
     "bse_to_bf16", "bse_dense_forward_bf16", "bse_continued_fraction_terminated",
@@ -82,6 +82,8 @@ def _load():
         "bse_plan_destroy": (None, [vp]),
         "bse_interp_matvec": (i32, [vp, vp, vp, i32, vp]),
         "bse_haydock_run": (i32, [vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]),
+        "bse_haydock_converge": (i32, [vp, vp, i32, i32, i32, dbl, vp, i32, dbl, dbl, vp, vp, vp, vp, vp, vp, vp,
+                                         vp]),
         "bse_continued_fraction": (i32, [vp, vp, i32, i32, vp, vp, i32, dbl, vp, i32, dbl, vp, vp, vp]),
         "bse_plan_set_timing": (i32, [vp, i32]),
         "bse_plan_get_timing": (i32, [vp, P(dbl), P(i64)]),
@@ -194,6 +196,14 @@ def bse_interp_matvec(plan, x, y, n_rhs, stream=None):
 def bse_haydock_run(plan, P, n_rhs, n_steps, a, b, pnorm2, steps_done, status, stream=None):
     _check(_lib.bse_haydock_run(plan, _ptr(P), int(n_rhs), int(n_steps), _ptr(a), _ptr(b), _ptr(pnorm2),
                                 _ptr(steps_done), _ptr(status), _stream(stream)), "bse_haydock_run")
+
+
+def bse_haydock_converge(plan, P, n_rhs, max_steps, check_every, prefactor, omega, n_omega, eta, tol, a, b, pnorm2,
+                         steps_done, status, eps_re, eps_im, stream=None):
+    _check(_lib.bse_haydock_converge(plan, _ptr(P), int(n_rhs), int(max_steps), int(check_every), float(prefactor),
+                                     _ptr(omega), int(n_omega), float(eta), float(tol), _ptr(a), _ptr(b),
+                                     _ptr(pnorm2), _ptr(steps_done), _ptr(status), _ptr(eps_re), _ptr(eps_im),
+                                     _stream(stream)), "bse_haydock_converge")
 
 
 def bse_continued_fraction(a, b, lda, ldb, pnorm2, steps, n_chains, prefactor, omega, n_omega, eta,
@@ -478,6 +488,28 @@ class BSEProblem:
         status = torch.empty(r, dtype=torch.int32, device=dev)
         bse_haydock_run(self.plan, P, r, n_steps, a, b, pn, steps, status)
         return dict(a=a, b=b, pnorm2=pn, steps=steps, status=status)
+
+    def haydock_converge(self, P, max_steps: int, omega, eta: float, prefactor: float, tol: float,
+                         check_every: int = 20):
+        """Chains run until eps2 changes by at most tol (relative to its peak) between
+        checks every check_every steps: (chain dict as haydock, eps [n_rhs, n_omega])."""
+        P = torch.as_tensor(P)
+        if P.dim() == 1:
+            P = P[None]
+        P = P.to(self.device).to(torch.complex128).contiguous()
+        r = P.shape[0]
+        dev = self.device
+        om = torch.as_tensor(np.asarray(omega, dtype=np.float64)).to(dev)
+        a = torch.empty(r, max_steps, dtype=torch.float64, device=dev)
+        b = torch.empty(r, max_steps + 1, dtype=torch.float64, device=dev)
+        pn = torch.empty(r, dtype=torch.float64, device=dev)
+        steps = torch.empty(r, dtype=torch.int32, device=dev)
+        status = torch.empty(r, dtype=torch.int32, device=dev)
+        er = torch.empty(r, om.numel(), dtype=torch.float64, device=dev)
+        ei = torch.empty_like(er)
+        bse_haydock_converge(self.plan, P, r, max_steps, check_every, prefactor, om, om.numel(), eta, tol, a, b, pn,
+                             steps, status, er, ei)
+        return dict(a=a, b=b, pnorm2=pn, steps=steps, status=status), torch.complex(er, ei)
 
     @staticmethod
     def continued_fraction(chain: dict, prefactor: float, omega, eta: float) -> torch.Tensor:

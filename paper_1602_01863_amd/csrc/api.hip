@@ -128,6 +128,7 @@ Layout make_layout(const Geometry& g) {
     L.rpart = take((size_t)g.ncells * R * 2 * sizeof(double));
     L.chain = take((size_t)2 * kMaxRhs * sizeof(ChainState));
     L.pend = take((size_t)kMaxRhs * sizeof(StepScalars));
+    L.flags = take((size_t)kMaxRhs * sizeof(int32_t));
     L.vec_a = take((size_t)g.N * R * vec_elem_bytes(g.dtype));
     L.vec_b = take((size_t)g.N * R * vec_elem_bytes(g.dtype));
     L.kq = L.kscale = L.qfrag = off;
@@ -209,26 +210,104 @@ hipError_t launch_continued_fraction(const double* a, const double* b, int lda, 
     return hipGetLastError();
 }
 
-hipError_t enqueue_haydock(Plan& p, const double* P, int n_rhs, int n_steps, double* a, double* b, double* pnorm2,
-                           int32_t* steps_done, int32_t* status, hipStream_t stream) {
-    const int lda = n_steps, ldb = n_steps + 1;
-    void* A = p.ws + p.L.vec_a;  // u_{i-1}, then w, then u_{i+1}
-    void* B = p.ws + p.L.vec_b;  // u_i
-    // u_1 = P, ||u_1||, ||P||, coarse vector of psi_1; zero-fills a and b
+// chain start: u_1 = P, ||u_1||, ||P||, coarse vector of psi_1; zero-fills a and b
+static hipError_t enqueue_chain_start(Plan& p, const double* P, int n_rhs, double* a, double* b, int lda, int ldb,
+                                      hipStream_t stream) {
+    void* B = p.ws + p.L.vec_b;  // u_1
     hipError_t e = launch_restrict(p, RESTRICT_INIT, nullptr, nullptr, nullptr, P, B, 0, a, b, lda, ldb, n_rhs,
                                    stream);
     if (e == hipSuccess) e = launch_collapse(p, COLLAPSE_INIT, 0, b, ldb, n_rhs, stream);
-    for (int i = 0; i < n_steps && e == hipSuccess; ++i) {
+    return e;
+}
+
+// steps i0 .. i1 - 1 of the chain (Eqs. ai-ci); the two vector buffers alternate: before
+// step i, buffer (i even ? vec_b : vec_a) holds u_i and the other u_{i-1}
+static hipError_t enqueue_chain_steps(Plan& p, int i0, int i1, int n_rhs, double* a, double* b, int lda, int ldb,
+                                      hipStream_t stream) {
+    hipError_t e = hipSuccess;
+    for (int i = i0; i < i1 && e == hipSuccess; ++i) {
+        void* B = p.ws + ((i & 1) ? p.L.vec_a : p.L.vec_b);  // u_i
+        void* A = p.ws + ((i & 1) ? p.L.vec_b : p.L.vec_a);  // u_{i-1}, then w, then u_{i+1}
         e = launch_m3_apply(p, B, n_rhs, stream);   // Method 3 band of u_i (no-op without a band)
         if (e == hipSuccess) e = launch_gemv(p, n_rhs, stream);
         if (e == hipSuccess) e = launch_prolong(p, PROLONG_LANCZOS, B, A, i, n_rhs, stream);
         if (e == hipSuccess)
             e = launch_restrict(p, RESTRICT_UPDATE, nullptr, A, B, nullptr, A, i, a, b, lda, ldb, n_rhs, stream);
         if (e == hipSuccess) e = launch_collapse(p, COLLAPSE_STEP, i, b, ldb, n_rhs, stream);
-        std::swap(A, B);
     }
+    return e;
+}
+
+hipError_t enqueue_haydock(Plan& p, const double* P, int n_rhs, int n_steps, double* a, double* b, double* pnorm2,
+                           int32_t* steps_done, int32_t* status, hipStream_t stream) {
+    const int lda = n_steps, ldb = n_steps + 1;
+    hipError_t e = enqueue_chain_start(p, P, n_rhs, a, b, lda, ldb, stream);
+    if (e == hipSuccess) e = enqueue_chain_steps(p, 0, n_steps, n_rhs, a, b, lda, ldb, stream);
     if (e == hipSuccess) e = launch_chain_report(p, n_steps, pnorm2, steps_done, status, n_rhs, stream);
     return e;
+}
+
+// ---- convergence check of the spectrum (the paper's stop rule, Sec. 2 after Eq. fraccont)
+// One block per chain: eps_M(omega) from the coefficients so far (Eq. fraccont), compared
+// with the previous check's eps2 at every omega.  A chain whose largest change is at most
+// tol times the largest |eps2| stops: its state is made inactive (status BSE_OK), so the
+// following steps leave its coefficients alone.  active_out[r] = chain still running.
+__global__ __launch_bounds__(1024) void k_converge_check(const double* __restrict__ a, const double* __restrict__ b,
+                                                         int lda, int ldb, ChainState* __restrict__ cs, double prefactor,
+                                                         const double* __restrict__ omega, int n_omega, double eta,
+                                                         double tol, int first, double* __restrict__ eps_re,
+                                                         double* __restrict__ eps_im, int32_t* __restrict__ active_out) {
+    __shared__ double sred[2][1024 / kWave];
+    const int r = blockIdx.x;
+    const ChainState st = cs[r];
+    const int m = min(st.steps, lda);
+    const double pn = st.pnorm2;
+    const double* ac = a + (int64_t)r * lda;
+    const double* bc = b + (int64_t)r * ldb;
+    double dmax = 0.0, emax = 0.0;
+    for (int w = threadIdx.x; w < n_omega; w += blockDim.x) {
+        double er = 1.0, ei = 0.0;
+        if (m > 0 && pn != 0.0) {
+            const double zr = omega[w], zi = eta;
+            double tr = zr - ac[m - 1], ti = zi;
+            for (int j = m - 2; j >= 0; --j) {
+                const double b2 = bc[j + 1] * bc[j + 1];
+                const double den = tr * tr + ti * ti;
+                tr = zr - ac[j] - b2 * tr / den;
+                ti = zi + b2 * ti / den;
+            }
+            const double den = tr * tr + ti * ti;
+            er = 1.0 - prefactor * pn * tr / den;
+            ei = prefactor * pn * ti / den;
+        }
+        const int64_t o = (int64_t)r * n_omega + w;
+        if (!first) dmax = fmax(dmax, fabs(ei - eps_im[o]));
+        emax = fmax(emax, fabs(ei));
+        eps_re[o] = er;
+        eps_im[o] = ei;
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        dmax = fmax(dmax, __shfl_xor(dmax, off, kWave));
+        emax = fmax(emax, __shfl_xor(emax, off, kWave));
+    }
+    const int wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    if (threadIdx.x % kWave == 0) {
+        sred[0][wave] = dmax;
+        sred[1][wave] = emax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < nw; ++w) {
+            dmax = fmax(dmax, sred[0][w]);
+            emax = fmax(emax, sred[1][w]);
+        }
+        int active = st.active;
+        if (active && !first && dmax <= tol * emax) {
+            cs[r].active = 0;   // converged: the chain stops here with status BSE_OK
+            active = 0;
+        }
+        active_out[r] = active;
+    }
 }
 
 }  // namespace bse
@@ -343,6 +422,8 @@ bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d, 
     p->ws = static_cast<char*>(workspace);
     p->n_split = 0;
     p->product_form = 0;
+    p->side = nullptr;
+    p->chk[0] = p->chk[1] = nullptr;
     p->restrict_group = 1;
     p->timing = 0;
     p->ev = nullptr;
@@ -377,6 +458,9 @@ void bse_plan_destroy(bse_plan* plan) {
     if (!plan) return;
     Plan* p = reinterpret_cast<Plan*>(plan);
     release_events(p);
+    for (int k = 0; k < 2; ++k)
+        if (p->chk[k]) (void)hipEventDestroy(p->chk[k]);
+    if (p->side) (void)hipStreamDestroy(p->side);
     delete p;
 }
 
@@ -417,6 +501,59 @@ bse_status bse_haydock_run(bse_plan* plan, const double* P, int32_t n_rhs, int32
     }
     hipError_t e = enqueue_haydock(p, P, n_rhs, n_steps, a, b, pnorm2, steps_done, status, stream);
     return e == hipSuccess ? BSE_OK : hip_fail(e, "bse_haydock_run");
+}
+
+bse_status bse_haydock_converge(bse_plan* plan, const double* P, int32_t n_rhs, int32_t max_steps,
+                                int32_t check_every, double prefactor, const double* omega, int32_t n_omega,
+                                double eta, double tol, double* a, double* b, double* pnorm2, int32_t* steps_done,
+                                int32_t* status, double* eps_re, double* eps_im, hipStream_t stream) {
+    if (!plan || !P || !a || !b || !pnorm2 || !steps_done || !status || !omega || !eps_re || !eps_im) {
+        set_error("bse_haydock_converge: NULL argument");
+        return BSE_ERR_INVALID_ARG;
+    }
+    Plan& p = *reinterpret_cast<Plan*>(plan);
+    if (n_rhs < 1 || n_rhs > p.g.max_rhs || max_steps < 1 || check_every < 1 || n_omega < 1 || !(eta > 0) ||
+        !(tol >= 0)) {
+        set_error("bse_haydock_converge: need n_rhs in [1, %d], max_steps, check_every, n_omega >= 1, eta > 0, "
+                  "tol >= 0", p.g.max_rhs);
+        return BSE_ERR_INVALID_ARG;
+    }
+    const int lda = max_steps, ldb = max_steps + 1;
+    int32_t* flags = reinterpret_cast<int32_t*>(p.ws + p.L.flags);
+    hipError_t e = hipSuccess;
+    if (!p.side) e = hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking);   // default priority
+    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+        if (!p.chk[k]) e = hipEventCreateWithFlags(&p.chk[k], hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "bse_haydock_converge: stream or events");
+    e = enqueue_chain_start(p, P, n_rhs, a, b, lda, ldb, stream);
+    int i = 0, c = 0;
+    bool running = true;
+    while (e == hipSuccess && i < max_steps) {
+        const int n = std::min(check_every, max_steps - i);
+        e = enqueue_chain_steps(p, i, i + n, n_rhs, a, b, lda, ldb, stream);
+        i += n;
+        if (e != hipSuccess) break;
+        ChainState* cs = reinterpret_cast<ChainState*>(p.ws + p.L.chain) + state_in(i) * kMaxRhs;
+        hipLaunchKernelGGL(k_converge_check, dim3(n_rhs), dim3(1024), 0, stream, a, b, lda, ldb, cs, prefactor, omega,
+                           n_omega, eta, tol, c == 0 ? 1 : 0, eps_re, eps_im, flags);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventRecord(p.chk[c & 1], stream);
+        // the previous check is read while this chunk runs: at most one chunk past the
+        // convergence is enqueued, and it leaves the stopped chains unchanged
+        if (e == hipSuccess && c > 0) {
+            int32_t act[kMaxRhs] = {0, 0, 0, 0};
+            e = hipEventSynchronize(p.chk[(c - 1) & 1]);
+            if (e == hipSuccess) e = hipMemcpyAsync(act, flags, n_rhs * sizeof(int32_t), hipMemcpyDeviceToHost, p.side);
+            if (e == hipSuccess) e = hipStreamSynchronize(p.side);
+            running = false;
+            for (int r = 0; r < n_rhs; ++r) running = running || act[r] != 0;
+        }
+        ++c;
+        if (!running) break;
+    }
+    if (e == hipSuccess) e = launch_chain_report(p, i, pnorm2, steps_done, status, n_rhs, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    return e == hipSuccess ? BSE_OK : hip_fail(e, "bse_haydock_converge");
 }
 
 bse_status bse_continued_fraction(const double* a, const double* b, int32_t lda, int32_t ldb, const double* pnorm2,

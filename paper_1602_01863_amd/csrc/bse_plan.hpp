@@ -100,7 +100,8 @@ inline bool kc_packable(int dtype) { return dtype == BSE_F32 || dtype == BSE_F32
 // restrict reads the overlaps in their input layout; kq, kscale, qfrag only for the
 // low-precision forms; kp, hpart, htab only for the FP32 coarse kernel
 struct Layout {
-    size_t qpart, qbar, rvec, gpart, ppart, rpart, chain, pend, vec_a, vec_b, dsw, kq, kscale, qfrag, kp, hpart, htab;
+    size_t qpart, qbar, rvec, gpart, ppart, rpart, chain, pend, flags, vec_a, vec_b, dsw, kq, kscale, qfrag, kp, hpart,
+        htab;
     size_t dsw_bytes, kq_bytes, kscale_bytes, qfrag_bytes, kp_bytes;
     size_t total;
 };
@@ -127,6 +128,9 @@ struct Plan {
     const char* m3_band;  // caller's band buffer: offset table, then the blocks
     double2* m3_yb;       // band product [rhs][N] (FP64), the tail of the band buffer
     int m3_noff_pad;      // band offsets, padded to whole chunks
+    // chains run to convergence: a side stream for reading the check flags, two events
+    hipStream_t side;
+    hipEvent_t chk[2];
 };
 
 // launches implemented in hotpath.hip (return hipSuccess or the launch error)

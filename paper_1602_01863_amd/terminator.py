@@ -5,9 +5,10 @@ unknown; the paper runs the chain until the spectrum stops changing.  Here a sma
 dense network (4 layers, width 128, GELU) predicts, from the first M_IN = 64
 coefficients of a chain, the next M_OUT = 192 coefficients and the asymptotic pair
 (a_inf, b_inf) that closes the fraction as a constant chain.  The chain can then
-stop after 64 steps; when an error estimate says the closed spectrum is not good
-enough, the full plain chain is run instead (the fallback, which is also the reference
-in the tests).
+stop after 64 steps, plus 32 that check the prediction (the error estimate: how far
+the closed spectrum moves when those computed coefficients replace the predicted
+ones); when the estimate says the closed spectrum is not good enough, the full plain
+chain is run instead (the fallback, which is also the reference in the tests).
 
 Everything runs in the library's kernels: training (FP32 dense layers, GELU, mean
 squared error, Adam) and inference (BF16 on the matrix cores), the chains (the
@@ -316,26 +317,40 @@ def predict_tail(net: TerminatorMLP, a, b, bf16=True):
     return A, B, ainf, binf
 
 
+K_CHECK = 32           # computed coefficients past the network's input that check its prediction
+
+
 def terminated_eps(net, a, b, pnorm2, prefactor, omega, eta, threshold=1e-3, bf16=True):
-    """eps_M from 64 computed coefficients: closed by the network's tail, with the error
-    estimate  est = ||eps2(network) - eps2(head closure)|| / ||eps2(network)||  per chain.
-    Chains with est > threshold are marked for the fallback (the full plain chain)."""
+    """eps_M closed by the network's tail, checked against K_CHECK more computed steps.
+
+    a, b hold M_IN + K_CHECK computed coefficients per chain.  The network predicts
+    a_65..a_256 from the first 64; the delivered spectrum (closure B) takes the computed
+    a_65..a_96, b_66..b_97 in place of the predicted ones and the prediction from there
+    on.  The error estimate is how far the spectrum moves when those 32 computed
+    coefficients replace the predicted ones,
+        est = ||eps2(B) - eps2(A)|| / ||eps2(B)||,  A = the 64 computed + all predicted,
+    i.e. the evidence the chain itself gives on the prediction (the paper's own stop rule
+    compares spectra of successive chain lengths in the same way).  Chains with
+    est > threshold are marked for the fallback (the full plain chain)."""
     A, B, ainf, binf = predict_tail(net, a, b, bf16=bf16)
-    e_net = closed_spectrum(A, B, pnorm2, ainf, binf, prefactor, omega, eta)
-    ha, hb = head_closure(a, b)
-    e_head = closed_spectrum(a[:, :M_IN], b[:, :M_IN + 1], pnorm2, ha, hb, prefactor, omega, eta)
-    est = np.linalg.norm(e_net.imag - e_head.imag, axis=1) / np.maximum(np.linalg.norm(e_net.imag, axis=1), 1e-300)
-    return e_net, est, est > threshold
+    e_a = closed_spectrum(A, B, pnorm2, ainf, binf, prefactor, omega, eta)
+    A2, B2 = A.copy(), B.copy()
+    A2[:, M_IN:M_IN + K_CHECK] = a[:, M_IN:M_IN + K_CHECK]
+    B2[:, M_IN + 1:M_IN + K_CHECK + 1] = b[:, M_IN + 1:M_IN + K_CHECK + 1]
+    e_b = closed_spectrum(A2, B2, pnorm2, ainf, binf, prefactor, omega, eta)
+    est = np.linalg.norm(e_b.imag - e_a.imag, axis=1) / np.maximum(np.linalg.norm(e_b.imag, axis=1), 1e-300)
+    return e_b, est, est > threshold
 
 
 def run_with_fallback(prob, P, net, n_full, prefactor, omega, eta, threshold=1e-3):
-    """Spectrum of the chains of prob for the start vectors P ([n_rhs, N]): 64 steps closed
-    by the network when its error estimate is <= threshold, else the plain chain of
+    """Spectrum of the chains of prob for the start vectors P ([n_rhs, N]): 96 steps
+    closed by the network when its error estimate is <= threshold, else the plain chain of
     n_full steps (the fallback).  Returns (eps_M [n_rhs, n_omega], fell_back [n_rhs])."""
-    ch = prob.haydock(P, M_IN)
+    m = M_IN + K_CHECK
+    ch = prob.haydock(P, m)
     a, b = ch["a"].cpu().numpy(), ch["b"].cpu().numpy()
     pn = ch["pnorm2"].cpu().numpy()
-    eps, est, fb = terminated_eps(net, a[:, :M_IN], b[:, :M_IN + 1], pn, prefactor, omega, eta, threshold)
+    eps, est, fb = terminated_eps(net, a[:, :m], b[:, :m + 1], pn, prefactor, omega, eta, threshold)
     if fb.any():
         full = prob.haydock(P, n_full)
         plain = prob.continued_fraction(full, prefactor, omega, eta).cpu().numpy()
@@ -387,13 +402,21 @@ def evaluate(net, n_problems=8, ref_steps=600, etas=(0.05, 0.1, 0.2), log=None):
 
     for eta in etas:
         ref = trunc(ref_steps, eta).imag
-        err = lambda e: float(np.mean(np.linalg.norm(e.imag - ref, axis=1) / np.linalg.norm(ref, axis=1)))
+        errs = lambda e: np.linalg.norm(e.imag - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        err = lambda e: float(np.mean(errs(e)))
+        A, Bq, ainf, binf = predict_tail(net, a, b)
+        e_net64 = closed_spectrum(A, Bq, pn, ainf, binf, C, om, eta)
         e_net, est, fb = terminated_eps(net, a, b, pn, C, om, eta)
         ha, hb = head_closure(a, b)
         e_head = closed_spectrum(a[:, :M_IN], b[:, :M_IN + 1], pn, ha, hb, C, om, eta)
+        true = errs(e_net)
+        acc = ~fb
         rows[str(eta)] = {"truncated_64": err(trunc(M_IN, eta)), "head_closure_64": err(e_head),
-                          "network_64": err(e_net), "plain_300": err(trunc(300, eta)),
-                          "fallback_fraction": float(fb.mean()), "estimate_mean": float(est.mean())}
+                          "network_64": err(e_net64), "network_96_checked": err(e_net),
+                          "plain_96": err(trunc(M_IN + K_CHECK, eta)), "plain_300": err(trunc(300, eta)),
+                          "fallback_fraction": float(fb.mean()), "estimate_mean": float(est.mean()),
+                          "accepted": int(acc.sum()), "false_accepts": int((acc & (true > 1e-3)).sum()),
+                          "worst_accepted_error": float(true[acc].max()) if acc.any() else None}
         if log:
             log(f"eta {eta}: {rows[str(eta)]}")
     return rows

@@ -10,7 +10,11 @@ polarisation are written:
 
 Each row: pol, pnorm2, steps, a_1..a_m, b_1..b_{m+1}.
 
-Usage: python tests/golden/make_oracle_chains.py c1
+With --long M only the FP64 chain is written, M steps long, as
+``<name>_oracle_chain_<M>.txt``: long enough for the spectrum at the workload's
+broadening to have converged (the reference of the converged-spectrum checks).
+
+Usage: python tests/golden/make_oracle_chains.py c1 [--long 1200]
 """
 
 from __future__ import annotations
@@ -35,8 +39,10 @@ def _rows(ch):
     return np.array(out)
 
 
-def main(name: str):
+def main(name: str, long_steps: int = 0):
     cfg = ti.get_config(name)
+    if long_steps:
+        cfg = cfg.with_(steps=long_steps)
     t0 = time.time()
     bs = ti.band_structure(cfg)
     Dv, Dc = O.overlaps(bs.vecs_coarse, bs.vecs_dense, cfg.n_coarse, cfg.n_div, cfg.nv, cfg.nc)
@@ -52,6 +58,10 @@ def main(name: str):
     t0 = time.time()
     ch = O.haydock(op.apply, bs.P_flat(), cfg.steps)
     print(f"fp64 chain {time.time() - t0:.1f} s", flush=True)
+    if long_steps:
+        np.savetxt(os.path.join(HERE, f"{name}_oracle_chain_{long_steps}.txt"), _rows(ch), fmt="%.17e",
+                   header=header.replace("(oracle only)", f"--long {long_steps} (oracle only)"))
+        return
     np.savetxt(os.path.join(HERE, f"{name}_oracle_chain.txt"), _rows(ch), fmt="%.17e",
                header=header)
     c64 = np.complex64
@@ -75,4 +85,10 @@ def main(name: str):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "c1")
+    args = sys.argv[1:]
+    long_steps = 0
+    if "--long" in args:
+        k = args.index("--long")
+        long_steps = int(args[k + 1])
+        del args[k:k + 2]
+    main(args[0] if args else "c1", long_steps)
