@@ -179,7 +179,7 @@ def main():
     lowp = dtype in ("bf16", "f16")
     mat_bytes = {"f64": 16, "f32": 8, "f32v64": 8, "bf16": 4, "f16": 4}[dtype]
     nbk = -(-Nc // 64)
-    packed = dtype in ("f32", "f32v64") and not args.full_stream
+    packed = dtype in ("f32", "f32v64", "f64") and not args.full_stream
     if lowp:   # 64 x 64 blocks in the format (zero-padded) + one FP32 scale per block
         kc_bytes = nbk * nbk * 64 * 64 * mat_bytes + nbk * nbk * 4
     elif packed:   # the 128 x 128 tiles on and above the diagonal (K_c Hermitian)
@@ -277,6 +277,7 @@ def main():
             "avg_ms": round(gemv_ms, 5), "launches": gemv_launches,
             "TFLOPs": round(gemv_flops / (gemv_ms * 1e-3) / 1e12, 3),
             "engine": ("matrix cores 16x16x32 " + dtype + ", FP32 in-block accumulation (HBM-bound)") if lowp
+            else ("VALU FP64 FMA on the packed Hermitian tiles (HBM-bound; no MFMA)") if packed and dtype == "f64"
             else ("VALU FP32 FMA on the packed Hermitian tiles, FP32 runs of 16 steps summed in FP64 "
                   "(HBM-bound; no MFMA)") if packed
             else "VALU FP64 FMA on " + ("FP64" if dtype == "f64" else "FP32") + " storage (HBM-bound; no MFMA)",
@@ -285,6 +286,8 @@ def main():
         },
         "roofline": {
             "kernel": ("coarse product r = K_c qbar (k_gemv_mfma + k_gemv_reduce)" if lowp
+                       else "coarse product r = K_c qbar, packed Hermitian tiles (k_hemv64 + k_hemv_reduce)"
+                       if packed and dtype == "f64"
                        else "coarse product r = K_c qbar, packed Hermitian tiles (k_hemv + k_hemv_reduce)"
                        if packed else "coarse product r = K_c qbar (k_gemv2 + k_gemv_reduce)"),
             "bound": "hbm",

@@ -145,10 +145,10 @@ Layout make_layout(const Geometry& g) {
     L.kp = L.hpart = L.htab = off;
     L.kp_bytes = 0;
     if (kc_packable(g.dtype)) {
-        const HemvShape h = hemv_shape(g.Nc);
+        const HemvShape h = hemv_shape(g.Nc, g.dtype);
         L.kp_bytes = (size_t)h.tiles * h.tile_bytes;
         L.kp = take(L.kp_bytes);
-        L.hpart = take((size_t)(h.blocks + h.tiles) * 128 * R * sizeof(float2));
+        L.hpart = take((size_t)(h.blocks + h.tiles) * 128 * R * h.elem_bytes);
         L.htab = take((size_t)(h.blocks + h.nbk + 1) * sizeof(int));
     }
     L.dsw_bytes = 0;

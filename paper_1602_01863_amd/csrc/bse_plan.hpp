@@ -85,20 +85,21 @@ inline bool kc_lowp(int dtype) { return dtype == BSE_BF16_KC || dtype == BSE_F16
 // Lanczos vectors in FP32 storage
 inline bool vec_is_f32(int dtype) { return dtype == BSE_F32 || kc_lowp(dtype); }
 
-// Packed Hermitian coarse product (FP32 coarse kernel): 128 x 128 tiles on and above the
+// Packed Hermitian coarse product (FP32 or FP64 coarse kernel): 128 x 128 tiles on and above the
 // diagonal, their partial sums and the block table (see gemv.hip)
 struct HemvShape {
     int nbk;            // tile rows: ceil(Nc / 128)
     int64_t tiles;      // nbk (nbk + 1) / 2
     int64_t blocks;     // groups of 2 tiles of one tile row
-    size_t tile_bytes;  // 128 x 128 complex FP32
+    size_t elem_bytes;  // one complex entry (and one partial): FP32 or FP64
+    size_t tile_bytes;  // 128 x 128 complex entries
 };
-HemvShape hemv_shape(int64_t Nc);
-inline bool kc_packable(int dtype) { return dtype == BSE_F32 || dtype == BSE_F32_VEC64; }
+HemvShape hemv_shape(int64_t Nc, int dtype);
+inline bool kc_packable(int dtype) { return dtype == BSE_F32 || dtype == BSE_F32_VEC64 || dtype == BSE_F64; }
 
 // workspace regions (byte offsets from the workspace base); dsw_bytes == 0 when the
 // restrict reads the overlaps in their input layout; kq, kscale, qfrag only for the
-// low-precision forms; kp, hpart, htab only for the FP32 coarse kernel
+// low-precision forms; kp, hpart, htab only for the FP32 and FP64 coarse kernels
 struct Layout {
     size_t qpart, qbar, rvec, gpart, ppart, rpart, chain, pend, flags, vec_a, vec_b, dsw, kq, kscale, qfrag, kp, hpart,
         htab;
@@ -115,7 +116,7 @@ struct Plan {
     const double* delta;
     char* ws;
     int n_split;  // 0 = automatic
-    int product_form;  // coarse product of the FP32 coarse kernel: 0 packed Hermitian tiles, 1 full stream
+    int product_form;  // coarse product of the FP32/FP64 coarse kernel: 0 packed Hermitian tiles, 1 full stream
     int restrict_group;  // right-hand sides per restrict block (1, or 3 for three)
     // kernel timing: 0 off, 1 the coarse product, 2 the Method 3 band product
     int timing;

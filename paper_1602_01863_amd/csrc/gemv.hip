@@ -701,15 +701,165 @@ __global__ __launch_bounds__(256, 4) void k_hemv(const f4v* __restrict__ kp, con
     }
 }
 
+// ---- the same product for the FP64 coarse kernel ----------------------------------------
+// Same tiles and lane roles; an entry is 16 bytes, so a step is two loads (rows L and
+// 64 + L, each a contiguous 1 KiB run of the wavefront), layout [tile][h][s][row][L].  Every
+// product and sum is FP64: the column partials stay in registers for the whole half (a 64-bit
+// rotate is two 32-bit DPP moves) and the partials are FP64.
+
+__device__ __forceinline__ double wave_rol1_d(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x134, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x134, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__global__ __launch_bounds__(256) void k_hemv_pack64(const double2* __restrict__ K, d2v* __restrict__ kp, int64_t Nc,
+                                                     int nbk) {
+    const int64_t unit = blockIdx.x;   // (tile, half, step group of 4)
+    const int64_t tile = unit / 32;
+    const int hs = (int)(unit % 32);
+    const int h = hs / 16, s = (hs % 16) * 4 + threadIdx.x / kWave;
+    const int L = threadIdx.x % kWave;
+    int I = 0;
+    while (I + 1 < nbk && hemv_tile_index(I + 1, I + 1, nbk) <= tile) ++I;
+    const int J = I + (int)(tile - hemv_tile_index(I, I, nbk));
+    const int64_t col = (int64_t)J * kHemvTile + 64 * h + ((L + s) & 63);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int64_t row = (int64_t)I * kHemvTile + 64 * e + L;
+        const double2 v = (row < Nc && col < Nc) ? K[row * Nc + col] : make_double2(0.0, 0.0);
+        kp[(((tile * 2 + h) * 64 + s) * 2 + e) * kWave + L] = d2v{v.x, v.y};
+    }
+}
+
+template <int NRHS, bool OFFDIAG>
+__device__ __forceinline__ void hemv_half64(const d2v* __restrict__ kp, const double2* qj,
+                                            const double2 (&qi)[2][NRHS], double (&d1)[2][NRHS][2],
+                                            double2* __restrict__ r2part, int I, int J, int h, int nbk, int L) {
+    constexpr int U = 4;   // steps whose loads are in flight together
+    const d2v* tp = kp + (hemv_tile_index(I, J, nbk) * 2 + h) * (64 * 2 * kWave) + L;
+    double a2[NRHS][2];
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) a2[r][0] = a2[r][1] = 0.0;
+#pragma unroll 1
+    for (int s0 = 0; s0 < 64; s0 += U) {
+        d2v kv[U][2];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) kv[u][e] = __builtin_nontemporal_load(tp + (int64_t)(((s0 + u) * 2 + e) * kWave));
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            __builtin_amdgcn_sched_barrier(0);
+            const int c = (L + s0 + u) & 63;
+            const double k0r = kv[u][0].x, k0i = kv[u][0].y, k1r = kv[u][1].x, k1i = kv[u][1].y;
+#pragma unroll
+            for (int r = 0; r < NRHS; ++r) {
+                const double2 q = qj[r * 64 + c];
+                d1[0][r][0] = fma(k0r, q.x, d1[0][r][0]);
+                d1[0][r][0] = fma(-k0i, q.y, d1[0][r][0]);
+                d1[0][r][1] = fma(k0r, q.y, d1[0][r][1]);
+                d1[0][r][1] = fma(k0i, q.x, d1[0][r][1]);
+                d1[1][r][0] = fma(k1r, q.x, d1[1][r][0]);
+                d1[1][r][0] = fma(-k1i, q.y, d1[1][r][0]);
+                d1[1][r][1] = fma(k1r, q.y, d1[1][r][1]);
+                d1[1][r][1] = fma(k1i, q.x, d1[1][r][1]);
+            }
+            if (OFFDIAG) {
+#pragma unroll
+                for (int r = 0; r < NRHS; ++r) {
+                    double re = a2[r][0], im = a2[r][1];
+                    re = fma(k0r, qi[0][r].x, re);
+                    re = fma(k0i, qi[0][r].y, re);
+                    re = fma(k1r, qi[1][r].x, re);
+                    re = fma(k1i, qi[1][r].y, re);
+                    im = fma(k0r, qi[0][r].y, im);
+                    im = fma(-k0i, qi[0][r].x, im);
+                    im = fma(k1r, qi[1][r].y, im);
+                    im = fma(-k1i, qi[1][r].x, im);
+                    a2[r][0] = wave_rol1_d(re);
+                    a2[r][1] = wave_rol1_d(im);
+                }
+            }
+        }
+    }
+    // after 64 steps every column partial is back on the lane of its column
+    if (OFFDIAG) {
+        double2* out = r2part + hemv_tile_index(I, J, nbk) * kHemvTile * NRHS;
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) out[(64 * h + L) * NRHS + r] = make_double2(a2[r][0], a2[r][1]);
+    }
+}
+
+template <int NRHS>
+__global__ __launch_bounds__(256, NRHS > 3 ? 2 : 4) void k_hemv64(const d2v* __restrict__ kp, const double2* __restrict__ qbar,
+                                                   const int* __restrict__ table, double2* __restrict__ r1part,
+                                                   double2* __restrict__ r2part, int Nc, int nbk) {
+    extern __shared__ double2 hsm[];
+    const int wave = threadIdx.x / kWave;
+    const int L = threadIdx.x % kWave;
+    const int code = table[blockIdx.x];
+    const int I = code & 0xffff, g = code >> 16;
+    const int J = I + 2 * g + (wave >> 1);
+    const int h = wave & 1;
+    const bool active = J < nbk;
+    double2* qj = hsm + wave * NRHS * 64;   // q_J of the half's 64 columns
+    double2 qi[2][NRHS];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int row = I * kHemvTile + 64 * e + L;
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) qi[e][r] = row < Nc ? qbar[(int64_t)row * NRHS + r] : make_double2(0.0, 0.0);
+    }
+    if (active) {
+        const int col = J * kHemvTile + 64 * h + L;
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r)
+            qj[r * 64 + L] = col < Nc ? qbar[(int64_t)col * NRHS + r] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double d1[2][NRHS][2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) d1[e][r][0] = d1[e][r][1] = 0.0;
+    if (active) {
+        if (J != I)
+            hemv_half64<NRHS, true>(kp, qj, qi, d1, r2part, I, J, h, nbk, L);
+        else
+            hemv_half64<NRHS, false>(kp, qj, qi, d1, r2part, I, J, h, nbk, L);
+    }
+    __syncthreads();
+    double2* red = hsm;   // [4][128][NRHS]
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r)
+            red[(wave * kHemvTile + 64 * e + L) * NRHS + r] = make_double2(d1[e][r][0], d1[e][r][1]);
+    __syncthreads();
+    for (int o = threadIdx.x; o < kHemvTile * NRHS; o += blockDim.x) {
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const double2 v = red[w * kHemvTile * NRHS + o];
+            re += v.x;
+            im += v.y;
+        }
+        r1part[(int64_t)blockIdx.x * kHemvTile * NRHS + o] = make_double2(re, im);
+    }
+}
+
 // r[i][rhs] = sum of the P1 partials of tile row b = i / 128 (its blocks in order), then of
 // the P2 partials of tiles (I, b), I < b, in order of I.  Eight lanes per output: lane k
 // adds partials k, k + 8, ... (FP64), then the eight sums are added in a fixed butterfly.
 constexpr int kHemvRedLanes = 8;
 
-template <int NRHS>
-__global__ __launch_bounds__(256) void k_hemv_reduce(const float2* __restrict__ r1part,
-                                                     const float2* __restrict__ r2part, const int* __restrict__ band0,
-                                                     double2* __restrict__ rout, int Nc, int nbk) {
+template <int NRHS, class PT>
+__global__ __launch_bounds__(256) void k_hemv_reduce(const PT* __restrict__ r1part, const PT* __restrict__ r2part,
+                                                     const int* __restrict__ band0, double2* __restrict__ rout, int Nc,
+                                                     int nbk) {
     const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kHemvRedLanes;
     const int k = threadIdx.x % kHemvRedLanes;
     const int64_t oc = min(o, (int64_t)Nc * NRHS - 1);   // lanes past the end: same work, no store
@@ -719,7 +869,7 @@ __global__ __launch_bounds__(256) void k_hemv_reduce(const float2* __restrict__ 
     const int n = np1 + b;   // P1 partials, then P2 partials of tiles (0, b) .. (b - 1, b)
     double re = 0.0, im = 0.0;
     for (int t0 = k; t0 < n; t0 += 4 * kHemvRedLanes) {
-        float2 v[4];
+        PT v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int t = min(t0 + u * kHemvRedLanes, n - 1);
@@ -741,22 +891,29 @@ __global__ __launch_bounds__(256) void k_hemv_reduce(const float2* __restrict__ 
     if (k == 0 && o < (int64_t)Nc * NRHS) rout[o] = make_double2(re, im);
 }
 
-HemvShape hemv_shape(int64_t Nc) {
+HemvShape hemv_shape(int64_t Nc, int dtype) {
     HemvShape h;
     h.nbk = (int)((Nc + kHemvTile - 1) / kHemvTile);
     h.tiles = (int64_t)h.nbk * (h.nbk + 1) / 2;
     int64_t b = 0;
     for (int I = 0; I < h.nbk; ++I) b += (h.nbk - I + 1) / 2;
     h.blocks = b;
-    h.tile_bytes = (size_t)kHemvTile * kHemvTile * sizeof(float2);
+    h.elem_bytes = dtype == BSE_F64 ? sizeof(double2) : sizeof(float2);
+    h.tile_bytes = (size_t)kHemvTile * kHemvTile * h.elem_bytes;
     return h;
 }
 
 hipError_t launch_hemv_pack(const Plan& p, hipStream_t s) {
     if (p.L.kp_bytes == 0) return hipSuccess;
-    const HemvShape h = hemv_shape(p.g.Nc);
-    hipLaunchKernelGGL(k_hemv_pack, dim3((unsigned)(h.tiles * 32)), dim3(kBlock), 0, s,
-                       reinterpret_cast<const float2*>(p.Kc), reinterpret_cast<f4v*>(p.ws + p.L.kp), p.g.Nc, h.nbk);
+    const HemvShape h = hemv_shape(p.g.Nc, p.g.dtype);
+    if (p.g.dtype == BSE_F64)
+        hipLaunchKernelGGL(k_hemv_pack64, dim3((unsigned)(h.tiles * 32)), dim3(kBlock), 0, s,
+                           reinterpret_cast<const double2*>(p.Kc), reinterpret_cast<d2v*>(p.ws + p.L.kp), p.g.Nc,
+                           h.nbk);
+    else
+        hipLaunchKernelGGL(k_hemv_pack, dim3((unsigned)(h.tiles * 32)), dim3(kBlock), 0, s,
+                           reinterpret_cast<const float2*>(p.Kc), reinterpret_cast<f4v*>(p.ws + p.L.kp), p.g.Nc,
+                           h.nbk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_hemv_table, dim3(1), dim3(kWave), 0, s, reinterpret_cast<int*>(p.ws + p.L.htab),
@@ -767,22 +924,37 @@ hipError_t launch_hemv_pack(const Plan& p, hipStream_t s) {
 template <int NRHS>
 static hipError_t hemv_t(Plan& p, hipStream_t s) {
     const Geometry& g = p.g;
-    const HemvShape h = hemv_shape(g.Nc);
+    const HemvShape h = hemv_shape(g.Nc, g.dtype);
     const int* tab = reinterpret_cast<const int*>(p.ws + p.L.htab);
+    const double2* qbar = reinterpret_cast<const double2*>(p.ws + p.L.qbar);
+    double2* rvec = reinterpret_cast<double2*>(p.ws + p.L.rvec);
+    const int64_t n_out = g.Nc * NRHS;
+    const dim3 rgrid((unsigned)((n_out * kHemvRedLanes + kBlock - 1) / kBlock));
+    hipError_t e;
+    if (g.dtype == BSE_F64) {
+        double2* r1 = reinterpret_cast<double2*>(p.ws + p.L.hpart);
+        double2* r2 = r1 + (size_t)h.blocks * kHemvTile * NRHS;
+        // q_J of 4 wavefronts x 64 columns, or the P1 sums of 4 x 128 rows
+        const size_t lds = (size_t)4 * kHemvTile * NRHS * sizeof(double2);
+        hipLaunchKernelGGL((k_hemv64<NRHS>), dim3((unsigned)h.blocks), dim3(kBlock), lds, s,
+                           reinterpret_cast<const d2v*>(p.ws + p.L.kp), qbar, tab, r1, r2, (int)g.Nc, h.nbk);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_hemv_reduce<NRHS, double2>), rgrid, dim3(kBlock), 0, s, r1, r2, tab + h.blocks, rvec,
+                           (int)g.Nc, h.nbk);
+        return hipGetLastError();
+    }
     float2* r1 = reinterpret_cast<float2*>(p.ws + p.L.hpart);
     float2* r2 = r1 + (size_t)h.blocks * kHemvTile * NRHS;
     // q_J and P2 sums of 4 wavefronts x 64 columns, or the P1 sums of 4 x 128 rows
     const size_t lds = std::max((size_t)4 * NRHS * 64 * (sizeof(float2) + sizeof(double2)),
                                 (size_t)4 * kHemvTile * NRHS * sizeof(double2));
     hipLaunchKernelGGL((k_hemv<NRHS>), dim3((unsigned)h.blocks), dim3(kBlock), lds, s,
-                       reinterpret_cast<const f4v*>(p.ws + p.L.kp), reinterpret_cast<const double2*>(p.ws + p.L.qbar),
-                       tab, r1, r2, (int)g.Nc, h.nbk);
-    hipError_t e = hipGetLastError();
+                       reinterpret_cast<const f4v*>(p.ws + p.L.kp), qbar, tab, r1, r2, (int)g.Nc, h.nbk);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t n_out = g.Nc * NRHS;
-    const int64_t n_thr = n_out * kHemvRedLanes;
-    hipLaunchKernelGGL((k_hemv_reduce<NRHS>), dim3((unsigned)((n_thr + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, r1,
-                       r2, tab + h.blocks, reinterpret_cast<double2*>(p.ws + p.L.rvec), (int)g.Nc, h.nbk);
+    hipLaunchKernelGGL((k_hemv_reduce<NRHS, float2>), rgrid, dim3(kBlock), 0, s, r1, r2, tab + h.blocks, rvec,
+                       (int)g.Nc, h.nbk);
     return hipGetLastError();
 }
 
@@ -814,8 +986,8 @@ hipError_t launch_gemv(Plan& p, int n_rhs, hipStream_t s) {
         (void)hipEventRecord(e0, s);
     }
     hipError_t err = kc_lowp(p.g.dtype)        ? gemv_lowp(p, n_rhs, s)
-                     : (p.g.dtype == BSE_F64) ? gemv_r<double2>(p, n_rhs, s)
                      : use_packed(p)          ? hemv_r(p, n_rhs, s)
+                     : (p.g.dtype == BSE_F64) ? gemv_r<double2>(p, n_rhs, s)
                                               : gemv_r<float2>(p, n_rhs, s);
     if (e1) (void)hipEventRecord(e1, s);
     return err;

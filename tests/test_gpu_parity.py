@@ -74,10 +74,12 @@ def test_coarse_kernel_matches_oracle(bse, cfg):
     prob32.close()
 
 
+@pytest.mark.parametrize("form", [0, 1], ids=["packed", "full"])
 @pytest.mark.parametrize("cfg", CASES, ids=IDS)
-def test_matvec_fp64_matches_oracle(bse, cfg):
+def test_matvec_fp64_matches_oracle(bse, cfg, form):
     op = oracle_operator(cfg)
     prob = _problem(bse, cfg, "f64")
+    bse.bse_plan_set_coarse_product(prob.plan, form)
     x = ti.random_vectors(op.N, cfg.n_pol, 101)
     y = prob.matvec(x).cpu().numpy()
     ref = op.apply(x)
@@ -129,6 +131,7 @@ def test_matvec_independent_of_product_splits(bse, splits):
     cfg = ti.get_config("c0")
     op = oracle_operator(cfg)
     prob = _problem(bse, cfg, "f64")
+    bse.bse_plan_set_coarse_product(prob.plan, 1)
     bse.bse_plan_set_gemv_splits(prob.plan, splits)
     x = ti.random_vectors(op.N, 1, 105)
     assert rel_l2(prob.matvec(x).cpu().numpy(), op.apply(x)) < 1e-13
@@ -173,12 +176,14 @@ PACKED_CASES = [ti.get_config("c0").with_(n_pol=4), ODD_NC,
 
 @pytest.mark.parametrize("cfg", PACKED_CASES, ids=[c.name for c in PACKED_CASES])
 @pytest.mark.parametrize("n_rhs", [1, 2, 3, 4])
-def test_matvec_packed_product_matches_oracle(bse, cfg, n_rhs):
-    """K_c read once per Hermitian pair of tiles (Eqs. bse1-bse2): within storage rounding
-    plus the bound of the product's FP32 arithmetic, and 2e-6 in relative L2; results
-    are reproducible bit for bit."""
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_matvec_packed_product_matches_oracle(bse, cfg, n_rhs, dtype):
+    """K_c read once per Hermitian pair of tiles (Eqs. bse1-bse2).  FP32 coarse kernel:
+    within storage rounding plus the bound of the product's FP32 arithmetic, and 2e-6 in
+    relative L2; FP64: the bound of a few FP64 operations per term and 1e-13.  Results are
+    reproducible bit for bit."""
     op = oracle_operator(cfg)
-    prob = _problem(bse, cfg, "f32")
+    prob = _problem(bse, cfg, dtype)
     x = ti.random_vectors(op.N, n_rhs, 110)
     xs = prob.vector(x)
     y = prob.matvec(xs)
@@ -186,8 +191,12 @@ def test_matvec_packed_product_matches_oracle(bse, cfg, n_rhs):
     assert torch.equal(y, y2)
     y = y.cpu().numpy().astype(complex)
     ref = op.apply(xs.cpu().numpy().astype(complex))
-    assert np.all(np.abs(y - ref) <= product_bound(op, x, U32, 10, fp32_kernel_factors(True)))
-    assert rel_l2(y, ref) < 2e-6
+    if dtype == "f64":
+        assert np.all(np.abs(y - ref) <= product_bound(op, x, U64, factors=64) + 1e-300)
+        assert rel_l2(y, ref) < 1e-13
+    else:
+        assert np.all(np.abs(y - ref) <= product_bound(op, x, U32, 10, fp32_kernel_factors(True)))
+        assert rel_l2(y, ref) < 2e-6
     prob.close()
 
 
