@@ -24,15 +24,16 @@
 
 #include "bse_device.hpp"
 #include "bse_plan.hpp"
+#include "chain_close.hpp"
 
 namespace bse {
 
 // ------------------------------------------------------------------------------------
 // collapse: qbar[(k~ NP + p) n_rhs + r] = s_r sum_z qpart[cell_of_corner(k~, z)][z][r][p]
 //
-// In a chain the collapse closes the step: every block adds the restrict's per-cell
-// ||u||^2 partials (same fixed order in every block), so all blocks agree on
-// b_{i+1} = ||u_{i+1}|| (Eq. bi), the breakdown test and s_{i+1} = 1 / b_{i+1};
+// In a chain the collapse closes the step (chain_close.hpp): every block adds the
+// restrict's per-cell ||u||^2 partials (same fixed order in every block), so all blocks
+// agree on b_{i+1} = ||u_{i+1}|| (Eq. bi), the breakdown test and s_{i+1} = 1 / b_{i+1};
 // block 0 writes b_{i+1} and the next copy of the chain state.
 // ------------------------------------------------------------------------------------
 template <int MODE>
@@ -43,9 +44,7 @@ __global__ __launch_bounds__(256) void k_collapse(const double2* __restrict__ qp
                                                   double* __restrict__ beta, int ldb, int step, double tol2,
                                                   int n_c, int np, int n_rhs, int64_t total,
                                                   unsigned short* __restrict__ qfrag, int qfmt) {
-    __shared__ double sred[2 * kMaxRhs][kBlock / kWave];
-    __shared__ double sscale[kMaxRhs];
-    const int ncells = n_c * n_c * n_c;
+    __shared__ CloseLds cl;
     // this thread's 8 (cell, corner) vectors: loaded first (indices clamped), so their
     // latency overlaps the chain reductions below
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -57,95 +56,8 @@ __global__ __launch_bounds__(256) void k_collapse(const double2* __restrict__ qp
     double2 qv[8];
 #pragma unroll
     for (int z = 0; z < 8; ++z) qv[z] = qpart[((int64_t)(cell_of_corner(k, z, n_c) * 8 + z) * n_rhs + r0) * np + p];
-    if (MODE != COLLAPSE_PLAIN) {
-        // per-thread partial sums of ||u||^2 (and ||P||^2) for every right-hand side,
-        // then one block reduction in a fixed order
-        const int nval = 2 * n_rhs;
-        double acc[2 * kMaxRhs];
-#pragma unroll
-        for (int q = 0; q < 2 * kMaxRhs; ++q) acc[q] = 0.0;
-        for (int c0 = 0; c0 < ncells; c0 += 2 * kBlock) {
-            double v[2][2 * kMaxRhs];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int c = min(c0 + (int)threadIdx.x + u * kBlock, ncells - 1);
-#pragma unroll
-                for (int q = 0; q < 2 * kMaxRhs; ++q) v[u][q] = q < nval ? rpart[(int64_t)c * nval + q] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-                if (c0 + (int)threadIdx.x + u * kBlock < ncells)
-#pragma unroll
-                    for (int q = 0; q < 2 * kMaxRhs; ++q) acc[q] += v[u][q];
-        }
-        const int wave = threadIdx.x / kWave;
-#pragma unroll
-        for (int q = 0; q < 2 * kMaxRhs; ++q) {
-            if (q >= nval) break;
-            const double w = wave_sum(acc[q]);
-            if (threadIdx.x % kWave == 0) sred[q][wave] = w;
-        }
-        __syncthreads();
-        for (int r = 0; r < n_rhs; ++r) {
-            double uu = 0.0, pp = 0.0;
-            for (int w = 0; w < kBlock / kWave; ++w) {
-                uu += sred[2 * r][w];
-                pp += sred[2 * r + 1][w];
-            }
-            if (MODE != COLLAPSE_INIT) pp = 0.0;
-            if (threadIdx.x != 0) continue;
-            ChainState nx;
-            double b = 0.0;
-            if (MODE == COLLAPSE_INIT) {
-                nx.pnorm2 = pp;
-                nx.s_prev = 0.0;
-                nx.b_cur = 0.0;
-                nx.steps = 0;
-                nx.pad = 0;
-                if (uu > 0.0 && isfinite(uu)) {
-                    nx.active = 1;
-                    nx.s_cur = 1.0 / sqrt(uu);
-                    nx.status = BSE_OK;
-                } else {
-                    nx.active = 0;
-                    nx.s_cur = 0.0;
-                    nx.status = (uu == 0.0) ? BSE_INFO_ZERO_START : BSE_ERR_NONFINITE;
-                }
-            } else {
-                const ChainState st = cs_in[r];
-                nx = st;
-                nx.s_prev = st.s_cur;
-                nx.s_cur = 0.0;
-                nx.b_cur = 0.0;
-                if (st.active) {
-                    const StepScalars sc = pend[r];
-                    if (!sc.ok) {
-                        nx.status = BSE_ERR_NONFINITE;
-                        nx.active = 0;
-                    } else {
-                        nx.steps = step + 1;   // a_{step+1} is valid
-                        if (!isfinite(uu)) {
-                            nx.status = BSE_ERR_NONFINITE;
-                            nx.active = 0;
-                        } else if (uu <= tol2 * sc.ww) {
-                            nx.status = BSE_INFO_INVARIANT_SUBSPACE;  // b_{i+1} = 0: exact chain end
-                            nx.active = 0;
-                        } else {
-                            b = sqrt(uu);
-                            nx.b_cur = b;
-                            nx.s_cur = 1.0 / b;
-                        }
-                    }
-                }
-            }
-            sscale[r] = nx.s_cur;
-            if (blockIdx.x == 0) {
-                cs_out[r] = nx;
-                if (MODE == COLLAPSE_STEP && b > 0.0) beta[(int64_t)r * ldb + step + 1] = b;
-            }
-        }
-        __syncthreads();
-    }
+    if (MODE != COLLAPSE_PLAIN)
+        close_chain_step<MODE>(rpart, n_c * n_c * n_c, cs_in, pend, cs_out, beta, ldb, step, tol2, n_rhs, cl);
     if (i >= total) return;
     double re = 0.0, im = 0.0;
 #pragma unroll
@@ -153,7 +65,7 @@ __global__ __launch_bounds__(256) void k_collapse(const double2* __restrict__ qp
         re += qv[z].x;
         im += qv[z].y;
     }
-    const double sc = (MODE == COLLAPSE_PLAIN) ? 1.0 : sscale[r0];   // psi = s u in a chain
+    const double sc = (MODE == COLLAPSE_PLAIN) ? 1.0 : cl.scale[r0];   // psi = s u in a chain
     qbar[i] = make_double2(sc * re, sc * im);
     if (qfmt != 0) {
         // low-precision forms: qbar as matrix-core B fragments (see gemv.hip), leading
