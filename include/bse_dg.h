@@ -69,10 +69,12 @@ typedef enum {
  * terms of the same format (its leading part and the remainder), so that K's
  * rounding (unit roundoff 2^-8 for BF16; 2^-11 for FP16 above 2^-14 of the block
  * scale, 2^-25 of the scale absolute below) dominates the error.  Products over one block accumulate in FP32 on the
- * matrix cores; block results are scaled and added in FP64.  For FP16, qbar is
- * multiplied by 2^9 before the conversion (and the product by 2^-9): this stays
- * in range for vectors of norm <= 1, as in the Haydock chain.  The input K_c,
- * the overlaps and the Lanczos vectors are complex FP32. */
+ * matrix cores; block results are scaled and added in FP64.  For FP16, each
+ * right-hand side of each 64-entry group of qbar is multiplied by the power of two
+ * that puts its largest entry in [2^14, 2^15) before the conversion (the block
+ * result is divided by it), so no input norm overflows the format or loses its
+ * relative accuracy to subnormals.  The input K_c, the overlaps and the Lanczos
+ * vectors are complex FP32. */
 typedef enum {
     BSE_F64 = 0,        /* kernel, overlaps, vectors: complex FP64 */
     BSE_F32 = 1,        /* kernel, overlaps, vectors: complex FP32 */

@@ -131,7 +131,7 @@ Layout make_layout(const Geometry& g) {
     L.flags = take((size_t)kMaxRhs * sizeof(int32_t));
     L.vec_a = take((size_t)g.N * R * vec_elem_bytes(g.dtype));
     L.vec_b = take((size_t)g.N * R * vec_elem_bytes(g.dtype));
-    L.kq = L.kscale = L.qfrag = off;
+    L.kq = L.kscale = L.qfrag = L.qsinv = off;
     L.kq_bytes = L.kscale_bytes = L.qfrag_bytes = 0;
     if (kc_lowp(g.dtype)) {
         const KqShape k = kq_shape(g.Nc);
@@ -141,6 +141,7 @@ Layout make_layout(const Geometry& g) {
         L.kq = take(L.kq_bytes);
         L.kscale = take(L.kscale_bytes);
         L.qfrag = take(L.qfrag_bytes);
+        L.qsinv = take((size_t)k.nb * kMaxRhs * sizeof(float));
     }
     L.kp = L.hpart = L.htab = off;
     L.kp_bytes = 0;

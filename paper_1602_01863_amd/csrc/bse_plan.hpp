@@ -98,11 +98,11 @@ HemvShape hemv_shape(int64_t Nc, int dtype);
 inline bool kc_packable(int dtype) { return dtype == BSE_F32 || dtype == BSE_F32_VEC64 || dtype == BSE_F64; }
 
 // workspace regions (byte offsets from the workspace base); dsw_bytes == 0 when the
-// restrict reads the overlaps in their input layout; kq, kscale, qfrag only for the
-// low-precision forms; kp, hpart, htab only for the FP32 and FP64 coarse kernels
+// restrict reads the overlaps in their input layout; kq, kscale, qfrag, qsinv (the FP16
+// form's qbar scales) only for the low-precision forms; kp, hpart, htab only for the FP32 and FP64 coarse kernels
 struct Layout {
-    size_t qpart, qbar, rvec, gpart, ppart, rpart, chain, pend, flags, vec_a, vec_b, dsw, kq, kscale, qfrag, kp, hpart,
-        htab;
+    size_t qpart, qbar, rvec, gpart, ppart, rpart, chain, pend, flags, vec_a, vec_b, dsw, kq, kscale, qfrag, qsinv, kp,
+        hpart, htab;
     size_t dsw_bytes, kq_bytes, kscale_bytes, qfrag_bytes, kp_bytes;
     size_t total;
 };

@@ -17,8 +17,8 @@ struct CloseLds {
     double scale[kMaxRhs];
 };
 
-// Requires blockDim.x == kBlock and every thread of the block; MODE is COLLAPSE_INIT or
-// COLLAPSE_STEP.  Thread r < n_rhs handles chain r; its state and step scalars are loaded
+// Requires every thread of the block, blockDim.x a multiple of 64 and at most kBlock; MODE
+// is COLLAPSE_INIT or COLLAPSE_STEP.  Thread r < n_rhs handles chain r; its state and step scalars are loaded
 // before the partial sums, so their latency overlaps them.  On return lds.scale[r] holds
 // s_{i+1} of chain r (0 for a chain that stopped), valid in every thread.
 template <int MODE>
@@ -40,17 +40,18 @@ __device__ __forceinline__ void close_chain_step(const double* __restrict__ rpar
     double acc[2 * kMaxRhs];
 #pragma unroll
     for (int q = 0; q < 2 * kMaxRhs; ++q) acc[q] = 0.0;
-    for (int c0 = 0; c0 < ncells; c0 += 2 * kBlock) {
+    const int nt = blockDim.x;
+    for (int c0 = 0; c0 < ncells; c0 += 2 * nt) {
         double v[2][2 * kMaxRhs];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int c = min(c0 + (int)threadIdx.x + u * kBlock, ncells - 1);
+            const int c = min(c0 + (int)threadIdx.x + u * nt, ncells - 1);
 #pragma unroll
             for (int q = 0; q < 2 * kMaxRhs; ++q) v[u][q] = q < nval ? rpart[(int64_t)c * nval + q] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u)
-            if (c0 + (int)threadIdx.x + u * kBlock < ncells)
+            if (c0 + (int)threadIdx.x + u * nt < ncells)
 #pragma unroll
                 for (int q = 0; q < 2 * kMaxRhs; ++q) acc[q] += v[u][q];
     }
@@ -64,7 +65,7 @@ __device__ __forceinline__ void close_chain_step(const double* __restrict__ rpar
     __syncthreads();
     if (r < n_rhs) {
         double uu = 0.0, pp = 0.0;
-        for (int w = 0; w < kBlock / kWave; ++w) {
+        for (int w = 0; w < nt / kWave; ++w) {
             uu += lds.red[2 * r][w];
             pp += lds.red[2 * r + 1][w];
         }

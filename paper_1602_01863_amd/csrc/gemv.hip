@@ -287,7 +287,7 @@ template <int FMT>
 struct Lowp;
 template <>
 struct Lowp<BSE_BF16_KC> {
-    static constexpr double qscale = 1.0;
+    static constexpr bool grouped = false;   // qbar unscaled (BF16 has FP32's range)
     __device__ static inline unsigned short enc(float v) { return enc_lowp(BSE_BF16_KC, v); }
     __device__ static inline f32x4 mfma(u32x4 a, u32x4 b, f32x4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
@@ -296,7 +296,7 @@ struct Lowp<BSE_BF16_KC> {
 };
 template <>
 struct Lowp<BSE_F16_KC> {
-    static constexpr double qscale = 512.0;  // qbar x 2^9 before the conversion
+    static constexpr bool grouped = true;    // qbar x a power of two per 64-column group and rhs
     __device__ static inline unsigned short enc(float v) { return enc_lowp(BSE_F16_KC, v); }
     __device__ static inline f32x4 mfma(u32x4 a, u32x4 b, f32x4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
@@ -377,8 +377,8 @@ constexpr int kMfmaUnroll = 2;  // 64-column blocks whose operands are in flight
 
 template <int FMT>
 __global__ __launch_bounds__(256) void k_gemv_mfma(const u32x4* __restrict__ kq, const float* __restrict__ kscale,
-                                                   const u32x4* __restrict__ qf, double* __restrict__ part, int Nc,
-                                                   int nb, int cpb, int n_rhs) {
+                                                   const u32x4* __restrict__ qf, const float* __restrict__ qsinv,
+                                                   double* __restrict__ part, int Nc, int nb, int cpb, int n_rhs) {
     const int bi = blockIdx.x % nb;
     const int sp = blockIdx.x / nb;
     const int rg = threadIdx.x / kWave;
@@ -387,11 +387,14 @@ __global__ __launch_bounds__(256) void k_gemv_mfma(const u32x4* __restrict__ kq,
     // this wavefront's 4 A fragments of block (bi, bj): (ks, part) = (0, re), (0, im), (1, re), (1, im)
     const u32x4* arow = kq + (int64_t)bi * nb * 16 * kWave + (rg * 4) * kWave + lane;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const double qinv = 1.0 / Lowp<FMT>::qscale;
+    // this lane's output column n = lane % 16 belongs to right-hand side n % 4; the FP16
+    // form divides out the scale the collapse gave that rhs in column group bj
+    const int rq = (lane % 16) & 3;
+    auto qinv = [&](int bj) -> float { return Lowp<FMT>::grouped ? qsinv[(int64_t)bj * kMaxRhs + rq] : 1.0f; };
     int bj = bj0;
     for (; bj + kMfmaUnroll <= bj1; bj += kMfmaUnroll) {
         u32x4 a[kMfmaUnroll][4], b[kMfmaUnroll][4];
-        float sc[kMfmaUnroll];
+        float sc[kMfmaUnroll], qi[kMfmaUnroll];
 #pragma unroll
         for (int u = 0; u < kMfmaUnroll; ++u) {
             const u32x4* ab = arow + (int64_t)(bj + u) * 16 * kWave;
@@ -401,6 +404,7 @@ __global__ __launch_bounds__(256) void k_gemv_mfma(const u32x4* __restrict__ kq,
 #pragma unroll
             for (int f = 0; f < 4; ++f) b[u][f] = qf[((int64_t)(2 * (bj + u) + (f >> 1)) * 2 + (f & 1)) * kWave + lane];
             sc[u] = kscale[(int64_t)bi * nb + bj + u];
+            qi[u] = qinv(bj + u);
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -410,7 +414,7 @@ __global__ __launch_bounds__(256) void k_gemv_mfma(const u32x4* __restrict__ kq,
             d = Lowp<FMT>::mfma(a[u][1], b[u][1], d);  // Ki x B2
             d = Lowp<FMT>::mfma(a[u][2], b[u][2], d);  // second 32 columns
             d = Lowp<FMT>::mfma(a[u][3], b[u][3], d);
-            const double w = (double)sc[u] * qinv;
+            const double w = (double)sc[u] * (double)qi[u];   // powers of two: exact
 #pragma unroll
             for (int e = 0; e < 4; ++e) acc[e] = fma(w, (double)d[e], acc[e]);
         }
@@ -421,7 +425,7 @@ __global__ __launch_bounds__(256) void k_gemv_mfma(const u32x4* __restrict__ kq,
 #pragma unroll
         for (int f = 0; f < 4; ++f)
             d = Lowp<FMT>::mfma(ab[f * kWave], qf[((int64_t)(2 * bj + (f >> 1)) * 2 + (f & 1)) * kWave + lane], d);
-        const double w = (double)kscale[(int64_t)bi * nb + bj] * qinv;
+        const double w = (double)kscale[(int64_t)bi * nb + bj] * (double)qinv(bj);
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[e] = fma(w, (double)d[e], acc[e]);
     }
@@ -452,13 +456,16 @@ static hipError_t gemv_lowp(Plan& p, int n_rhs, hipStream_t s) {
     const u32x4* kq = reinterpret_cast<const u32x4*>(p.ws + p.L.kq);
     const float* ksc = reinterpret_cast<const float*>(p.ws + p.L.kscale);
     const u32x4* qf = reinterpret_cast<const u32x4*>(p.ws + p.L.qfrag);
+    const float* qsi = reinterpret_cast<const float*>(p.ws + p.L.qsinv);
     double* part = reinterpret_cast<double*>(p.ws + p.L.gpart);
     double2* rvec = reinterpret_cast<double2*>(p.ws + p.L.rvec);
     dim3 grid((unsigned)(k.nb * ns)), block(kBlock);
     if (g.dtype == BSE_BF16_KC)
-        hipLaunchKernelGGL(k_gemv_mfma<BSE_BF16_KC>, grid, block, 0, s, kq, ksc, qf, part, (int)g.Nc, k.nb, cpb, n_rhs);
+        hipLaunchKernelGGL(k_gemv_mfma<BSE_BF16_KC>, grid, block, 0, s, kq, ksc, qf, qsi, part, (int)g.Nc, k.nb, cpb,
+                           n_rhs);
     else
-        hipLaunchKernelGGL(k_gemv_mfma<BSE_F16_KC>, grid, block, 0, s, kq, ksc, qf, part, (int)g.Nc, k.nb, cpb, n_rhs);
+        hipLaunchKernelGGL(k_gemv_mfma<BSE_F16_KC>, grid, block, 0, s, kq, ksc, qf, qsi, part, (int)g.Nc, k.nb, cpb,
+                           n_rhs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t n_out = g.Nc * n_rhs;

@@ -43,8 +43,10 @@ __global__ __launch_bounds__(256) void k_collapse(const double2* __restrict__ qp
                                                   const double* __restrict__ rpart, ChainState* __restrict__ cs_out,
                                                   double* __restrict__ beta, int ldb, int step, double tol2,
                                                   int n_c, int np, int n_rhs, int64_t total,
-                                                  unsigned short* __restrict__ qfrag, int qfmt) {
+                                                  unsigned short* __restrict__ qfrag, int qfmt,
+                                                  float* __restrict__ qsinv) {
     __shared__ CloseLds cl;
+    __shared__ unsigned smax[kMaxRhs];
     // this thread's 8 (cell, corner) vectors: loaded first (indices clamped), so their
     // latency overlaps the chain reductions below
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -58,7 +60,6 @@ __global__ __launch_bounds__(256) void k_collapse(const double2* __restrict__ qp
     for (int z = 0; z < 8; ++z) qv[z] = qpart[((int64_t)(cell_of_corner(k, z, n_c) * 8 + z) * n_rhs + r0) * np + p];
     if (MODE != COLLAPSE_PLAIN)
         close_chain_step<MODE>(rpart, n_c * n_c * n_c, cs_in, pend, cs_out, beta, ldb, step, tol2, n_rhs, cl);
-    if (i >= total) return;
     double re = 0.0, im = 0.0;
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
@@ -66,12 +67,30 @@ __global__ __launch_bounds__(256) void k_collapse(const double2* __restrict__ qp
         im += qv[z].y;
     }
     const double sc = (MODE == COLLAPSE_PLAIN) ? 1.0 : cl.scale[r0];   // psi = s u in a chain
-    qbar[i] = make_double2(sc * re, sc * im);
+    re *= sc;
+    im *= sc;
+    double qs = 1.0;
+    if (qfmt == BSE_F16_KC) {
+        // FP16: the block is one 64-column group of qbar (64 n_rhs threads); each
+        // right-hand side of the group gets the power of two that puts its largest entry
+        // in [2^14, 2^15), so no encoding overflows whatever the vector's norm; the
+        // product divides it out with the block scale of K_c
+        if ((int)threadIdx.x < n_rhs) smax[threadIdx.x] = 0u;
+        __syncthreads();
+        if (i < total) atomicMax(&smax[r0], __float_as_uint((float)fmax(fabs(re), fabs(im))));
+        __syncthreads();
+        // m < 2^e; a zero or non-finite group keeps the scale 1
+        auto expo = [](float m) { return (m > 0.0f && isfinite(m)) ? ilogbf(m) + 1 : 15; };
+        qs = ldexp(1.0, 15 - expo(__uint_as_float(smax[r0])));
+        if ((int)threadIdx.x < n_rhs)
+            qsinv[(int64_t)blockIdx.x * kMaxRhs + threadIdx.x] = ldexpf(1.0f, expo(__uint_as_float(smax[threadIdx.x])) - 15);
+    }
+    if (i >= total) return;
+    qbar[i] = make_double2(re, im);
     if (qfmt != 0) {
         // low-precision forms: qbar as matrix-core B fragments (see gemv.hip), leading
         // part and remainder in the storage format, two variants per 32-column step
-        const double qs = qfmt == BSE_F16_KC ? 512.0 : 1.0;
-        const double vr = sc * re * qs, vi = sc * im * qs;
+        const double vr = re * qs, vi = im * qs;
         const unsigned short hr = enc_lowp(qfmt, (float)vr), hi = enc_lowp(qfmt, (float)vi);
         const unsigned short lr = enc_lowp(qfmt, (float)(vr - (double)dec_lowp(qfmt, hr)));
         const unsigned short li = enc_lowp(qfmt, (float)(vi - (double)dec_lowp(qfmt, hi)));
@@ -164,7 +183,11 @@ hipError_t launch_prolong(const Plan& p, int mode, const void* x, void* out, int
 hipError_t launch_collapse(const Plan& p, int mode, int step, double* b, int ldb, int n_rhs, hipStream_t s) {
     const Geometry& g = p.g;
     const int64_t total = g.Nc * n_rhs;
-    const int nb = (int)((total + kBlock - 1) / kBlock);
+    // FP16 coarse kernel: one block per 64-column group of qbar (see k_collapse)
+    const bool grouped = g.dtype == BSE_F16_KC;
+    const int bt = grouped ? kKqBlock * n_rhs : kBlock;
+    const int nb = grouped ? kq_shape(g.Nc).nb : (int)((total + kBlock - 1) / kBlock);
+    float* qsinv = grouped ? reinterpret_cast<float*>(p.ws + p.L.qsinv) : nullptr;
     const double2* qpart = reinterpret_cast<const double2*>(p.ws + p.L.qpart);
     double2* qbar = reinterpret_cast<double2*>(p.ws + p.L.qbar);
     ChainState* cs = reinterpret_cast<ChainState*>(p.ws + p.L.chain);
@@ -177,14 +200,14 @@ hipError_t launch_collapse(const Plan& p, int mode, int step, double* b, int ldb
     const ChainState* cin = cs + state_in(step) * kMaxRhs;
     ChainState* cout = (mode == COLLAPSE_INIT) ? cs : cs + state_out(step) * kMaxRhs;
     if (mode == COLLAPSE_PLAIN)
-        hipLaunchKernelGGL(k_collapse<COLLAPSE_PLAIN>, dim3(nb), dim3(kBlock), 0, s, qpart, qbar, cin, pend, rpart,
-                           cout, b, ldb, step, tol * tol, g.n_c, g.np, n_rhs, total, qf, qfmt);
+        hipLaunchKernelGGL(k_collapse<COLLAPSE_PLAIN>, dim3(nb), dim3(bt), 0, s, qpart, qbar, cin, pend, rpart,
+                           cout, b, ldb, step, tol * tol, g.n_c, g.np, n_rhs, total, qf, qfmt, qsinv);
     else if (mode == COLLAPSE_INIT)
-        hipLaunchKernelGGL(k_collapse<COLLAPSE_INIT>, dim3(nb), dim3(kBlock), 0, s, qpart, qbar, cin, pend, rpart,
-                           cout, b, ldb, step, tol * tol, g.n_c, g.np, n_rhs, total, qf, qfmt);
+        hipLaunchKernelGGL(k_collapse<COLLAPSE_INIT>, dim3(nb), dim3(bt), 0, s, qpart, qbar, cin, pend, rpart,
+                           cout, b, ldb, step, tol * tol, g.n_c, g.np, n_rhs, total, qf, qfmt, qsinv);
     else
-        hipLaunchKernelGGL(k_collapse<COLLAPSE_STEP>, dim3(nb), dim3(kBlock), 0, s, qpart, qbar, cin, pend, rpart,
-                           cout, b, ldb, step, tol * tol, g.n_c, g.np, n_rhs, total, qf, qfmt);
+        hipLaunchKernelGGL(k_collapse<COLLAPSE_STEP>, dim3(nb), dim3(bt), 0, s, qpart, qbar, cin, pend, rpart,
+                           cout, b, ldb, step, tol * tol, g.n_c, g.np, n_rhs, total, qf, qfmt, qsinv);
     return hipGetLastError();
 }
 

@@ -52,8 +52,10 @@ def lowp_bound(op, x, dtype):
       (`product_bound` with the FP32 unit).
     - K_c in the format: |dK| <= u |K| per entry, plus for FP16 an absolute floor
       of half the subnormal spacing, 2^-25 s_B <= 2^-24 max|K| (s_B < 2 max|K_B|).
-    - qbar as leading part + remainder in the format: relative u^2 (+ an absolute
-      floor 2^-25 / 2^9 for FP16, which scales qbar by 2^9).
+    - qbar as leading part + remainder in the format: relative u^2, plus for FP16 an
+      absolute floor of half the subnormal spacing over the group's scale: each 64-entry
+      group of qbar is scaled by the power of two that puts its largest entry in
+      [2^14, 2^15), so the floor is at most 2^-25 2^-14 max|qbar| <= 2^-39 max(|C||x|).
     - FP32 accumulation of the 64 products of one block: 64 u32 per |term|.
     - the restrict's and prolong's FP32 contractions: FP32_INNER_UNITS u32.
     The kernel terms are bounded by |C|^H |K| |C| |x|.
@@ -67,7 +69,8 @@ def lowp_bound(op, x, dtype):
         colsum = np.abs(aop.restrict(ax)).sum(axis=1)                # 1^T |C||x| per rhs
         w = np.abs(aop.prolong(np.ones((1, op.Nc))))                  # |C|^H 1
         rowk = np.abs(aop.prolong(np.abs(op.Kc).sum(axis=1)[None]))   # |C|^H |K| 1
-        bound = bound + 2.0 ** -24 * kmax * colsum[:, None] * w + 2.0 ** -34 * rowk
+        qmax = np.abs(aop.restrict(ax)).max(axis=1)                  # >= max|qbar| per rhs
+        bound = bound + 2.0 ** -24 * kmax * colsum[:, None] * w + 2.0 ** -39 * qmax[:, None] * rowk
     return bound
 
 
@@ -85,6 +88,30 @@ def test_matvec_lowp_within_format_bound(bse, cfg, dtype):
     assert np.all(np.isfinite(y))
     assert np.all(np.abs(y - ref) <= lowp_bound(op, xr, dtype))
     # the kernel part carries the format's rounding: far below one unit overall
+    assert rel_l2(y - op.delta[None] * xr, ref - op.delta[None] * xr) < 2 * UNIT[dtype]
+    prob.close()
+
+
+@pytest.mark.parametrize("norm", [1e4, 1e-6])
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_matvec_lowp_any_input_norm(bse, dtype, norm):
+    """A plain matvec of a vector far from unit norm: with norm 1e4 the entries of qbar
+    reach about 800, past the 128 that FP16 held at the former fixed scale of 2^9, and
+    with 1e-6 they would fall into its subnormals.  Each group of qbar carries its own power-of-two scale, so
+    the product stays finite and within the same componentwise bound at any norm."""
+    cfg = CASES[1]
+    op = oracle_operator(cfg)
+    prob = _problem(bse, cfg, dtype)
+    x = ti.random_vectors(op.N, cfg.n_pol, 303)
+    x = norm * x / np.linalg.norm(x, axis=1, keepdims=True)
+    xs = prob.vector(x)
+    y = prob.matvec(xs).cpu().numpy().astype(complex)
+    xr = xs.cpu().numpy().astype(complex)
+    ref = op.apply(xr)
+    assert np.all(np.isfinite(y))
+    if norm > 1:
+        assert np.abs(op.restrict(xr)).max() > 65504 / 512       # past the former fixed scale
+    assert np.all(np.abs(y - ref) <= lowp_bound(op, xr, dtype))
     assert rel_l2(y - op.delta[None] * xr, ref - op.delta[None] * xr) < 2 * UNIT[dtype]
     prob.close()
 
