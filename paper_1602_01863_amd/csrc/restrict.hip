@@ -310,7 +310,7 @@ __global__ __launch_bounds__(256, (NR == 1 && sizeof(M2) == 8 && NV * NC <= 18) 
     constexpr int EPT = 8;
     cd ua[EPT], pb[EPT];
     auto gidx = [&](int f) {
-        const int r = f / nelem;
+        const int r = NR == 1 ? 0 : f / nelem;   // one right-hand side: no division
         return (int64_t)(rhs0 + r) * N + cbase + (f - r * nelem);
     };
     auto load_batch = [&](int f0) {
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(256, (NR == 1 && sizeof(M2) == 8 && NV * NC <= 18) 
             for (int e = 0; e < EPT; ++e) {
                 const int f = f0 + t + e * kBlock;
                 if (f >= ntot) continue;
-                const int r = f / nelem;
+                const int r = NR == 1 ? 0 : f / nelem;
                 st(xs + r * xstride + (f - r * nelem), ua[e]);
             }
         }
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(256, (NR == 1 && sizeof(M2) == 8 && NV * NC <= 18) 
             for (int e = 0; e < EPT; ++e) {
                 const int f = f0 + t + e * kBlock;
                 if (f >= ntot) continue;
-                const int r = f / nelem;
+                const int r = NR == 1 ? 0 : f / nelem;
                 const int i = f - r * nelem;
                 double cr = 0.0;
                 bool okr = true;
