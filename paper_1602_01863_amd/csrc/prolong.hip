@@ -140,7 +140,9 @@ constexpr int prolong3_threads() {
     return 128 * (NR < 2 ? 2 : NR);
 }
 
-template <class M2, class V2, int NV, int NC, int MODE, int NR>
+// NDIV3 > 0: the subpoint count n_div^3 fixed at compile time (the LDS offsets of the
+// corner loop become immediates); 0: taken from n_div
+template <class M2, class V2, int NV, int NC, int MODE, int NR, int NDIV3>
 __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, V2, NV, NC, NR>())) void k_prolong3(const M2* __restrict__ d, const double* __restrict__ delta,
                                                          const double2* __restrict__ rvec, const V2* __restrict__ x,
                                                          V2* __restrict__ out, double* __restrict__ ppart,
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, V2, NV,
     extern __shared__ double2 lds2[];
     __shared__ double red[NR][NT / kWave][2];
     __shared__ double ftab[8 * kWave];
-    const int ndiv3 = n_div * n_div * n_div;
+    const int ndiv3 = NDIV3 > 0 ? NDIV3 : n_div * n_div * n_div;
     const int blk = NE * ndiv3;                // entries of one (cell, corner) block
     const int blku = (blk + U::P - 1) / U::P;  // its 16-byte units (blocks start 16-byte aligned)
     using IT = typename Inner<M2>::t;   // precision of the per-(subpoint, corner) contractions
@@ -433,11 +435,14 @@ static void prolong3_go(const Plan& p, int mode, const V2* xv, V2* ov, const Cha
     const double2* yb = p.m3_band ? p.m3_yb : nullptr;
     dim3 grid(g.ncells), block(prolong3_threads<NR>());
     if (mode == PROLONG_PLAIN)
-        hipLaunchKernelGGL((k_prolong3<M2, V2, NV, NC, PROLONG_PLAIN, NR>), grid, block, lds, s, d, p.delta, rvec, xv,
-                           ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, yb);
-    else
-        hipLaunchKernelGGL((k_prolong3<M2, V2, NV, NC, PROLONG_LANCZOS, NR>), grid, block, lds, s, d, p.delta, rvec,
+        hipLaunchKernelGGL((k_prolong3<M2, V2, NV, NC, PROLONG_PLAIN, NR, 0>), grid, block, lds, s, d, p.delta, rvec,
                            xv, ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, yb);
+    else if (g.ndiv3 == 64)   // 4 divisions per axis, the chain's common case
+        hipLaunchKernelGGL((k_prolong3<M2, V2, NV, NC, PROLONG_LANCZOS, NR, 64>), grid, block, lds, s, d, p.delta,
+                           rvec, xv, ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, yb);
+    else
+        hipLaunchKernelGGL((k_prolong3<M2, V2, NV, NC, PROLONG_LANCZOS, NR, 0>), grid, block, lds, s, d, p.delta,
+                           rvec, xv, ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, yb);
 }
 
 template <class M2, class V2, int NV, int NC>
