@@ -90,7 +90,8 @@ inline bool vec_is_f32(int dtype) { return dtype == BSE_F32 || kc_lowp(dtype); }
 struct HemvShape {
     int nbk;            // tile rows: ceil(Nc / 128)
     int64_t tiles;      // nbk (nbk + 1) / 2
-    int64_t blocks;     // groups of 2 tiles of one tile row
+    int tpw;            // tiles each wavefront streams in turn (gemv.hip)
+    int64_t blocks;     // groups of 2 tpw consecutive tiles of one tile row
     size_t elem_bytes;  // one complex entry (and one partial): FP32 or FP64
     size_t tile_bytes;  // 128 x 128 complex entries
 };

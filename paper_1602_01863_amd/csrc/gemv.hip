@@ -474,7 +474,7 @@ static hipError_t gemv_lowp(Plan& p, int n_rhs, hipStream_t s) {
     return hipGetLastError();
 }
 
-// ---- packed Hermitian product (FP32 coarse kernel) -------------------------------------
+// ---- packed Hermitian product (FP32 coarse kernel; the FP64 form follows) --------------
 //
 // K_c is Hermitian (Eqs. bse1-bse2), so its 128 x 128 tiles (I, J) with I <= J hold all of
 // it: half the bytes of the full stream.  One wavefront streams one 64-column half of a
@@ -489,12 +489,20 @@ static hipError_t gemv_lowp(Plan& p, int n_rhs, hipStream_t s) {
 // holds; after 64 steps every partial is back on the lane of its column.
 // Arithmetic: products and sums in FP32 over runs of kHemvFlush steps (P1: kHemvFlush terms
 // per row, P2: 2 kHemvFlush terms per column), then added into FP64 (P1 in registers, P2 in
-// LDS).  A block is 4 wavefronts on the two halves of 2 consecutive tiles of one tile row:
-// their P1 sums are added in LDS in a fixed order and written as one partial of r_I; every
-// off-diagonal tile writes its P2 partial of r_J.  k_hemv_reduce adds, for each output, the
+// LDS).  A block is 4 wavefronts on the two halves of 2 tpw consecutive tiles of one tile
+// row, each wavefront taking tpw of them in turn: their P1 sums are added in LDS
+// in a fixed order and written as one partial of r_I; every off-diagonal tile writes its P2
+// partial of r_J.  k_hemv_reduce adds, for each output, the
 // partials of its tile row and of its tile column in a fixed order.
 
 constexpr int kHemvTile = 128;
+// Tiles each wavefront streams one after another (tpw): a block covers 2 tpw consecutive
+// tiles of its tile row.  The plan takes the smallest tpw that keeps the grid within
+// kHemvBlocks blocks, a single round on the device with room to spare: a second, partial
+// round of blocks left the HBM stream short of loads in flight, and so did fewer, longer
+// blocks (9216-row kernel, FP32: 77.3 us at tpw 1 with 1332 blocks, 74.2 us at tpw 3 with
+// 468, 85.6 us at tpw 4 with 360).
+constexpr int kHemvBlocks = 512;
 constexpr int kHemvFlush = 16;   // steps per FP32 run before the FP64 sums
 constexpr int kHemvUnroll = 8;   // 16-byte loads of a lane in flight
 
@@ -525,13 +533,15 @@ __global__ __launch_bounds__(256) void k_hemv_pack(const float2* __restrict__ K,
     kp[((tile * 2 + h) * 64 + s) * kWave + L] = f4v{a.x, a.y, b.x, b.y};
 }
 
-// block -> (tile row I, group g of 2 tiles): table[b] = I | g << 16; band0[I] = first block of row I
-__global__ void k_hemv_table(int* __restrict__ table, int* __restrict__ band0, int nbk) {
+__host__ __device__ inline int hemv_groups(int nbk, int I, int tpw) { return (nbk - I + 2 * tpw - 1) / (2 * tpw); }
+
+// block -> (tile row I, group g of 2 tpw tiles): table[b] = I | g << 16; band0[I] = first block of row I
+__global__ void k_hemv_table(int* __restrict__ table, int* __restrict__ band0, int nbk, int tpw) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int b = 0;
     for (int I = 0; I < nbk; ++I) {
         band0[I] = b;
-        const int ng = (nbk - I + 1) / 2;
+        const int ng = hemv_groups(nbk, I, tpw);
         for (int g = 0; g < ng; ++g) table[b++] = I | (g << 16);
     }
     band0[nbk] = b;
@@ -636,26 +646,23 @@ __device__ __forceinline__ void hemv_half(const f4v* __restrict__ kp, const floa
     }
 }
 
-// Block = 4 wavefronts on 2 consecutive tiles of tile row I (wavefront w: tile J =
-// I + 2 g + w / 2, column half w % 2).
+// Block = 4 wavefronts on 2 tpw consecutive tiles of tile row I: wavefront w takes column
+// half w % 2 of the tiles J = I + 2 tpw g + w / 2 + 2 k, k < tpw, one after another.
 template <int NRHS>
 __global__ __launch_bounds__(256, 4) void k_hemv(const f4v* __restrict__ kp, const double2* __restrict__ qbar,
                                                  const int* __restrict__ table, float2* __restrict__ r1part,
-                                                 float2* __restrict__ r2part, int Nc, int nbk) {
+                                                 float2* __restrict__ r2part, int Nc, int nbk, int tpw) {
     extern __shared__ double2 hsm[];
     const int wave = threadIdx.x / kWave;
     const int L = threadIdx.x % kWave;
     const int code = table[blockIdx.x];
     const int I = code & 0xffff, g = code >> 16;
-    const int J = I + 2 * g + (wave >> 1);
     const int h = wave & 1;
-    const bool active = J < nbk;       // wavefront-uniform
-    const bool offdiag = J != I;
     // LDS: q_J of each wavefront's 64 columns [4][NRHS][64] (float2), then the FP64 P2 sums
-    // [4][NRHS][64]; at the end the P1 sums [4][128][NRHS] (double2) over both
+    // [4][NRHS][64]; at the end the P1 sums [4][128][NRHS] (double2) over all of them
     float2* qj = reinterpret_cast<float2*>(hsm) + wave * NRHS * 64;
     double2* p2 = hsm + 4 * NRHS * 64 / 2 + wave * NRHS * 64;
-    // q_I of this lane's two rows (FP32) and q_J of the half's columns in LDS
+    // q_I of this lane's two rows (FP32)
     float2 qi[2][NRHS];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -666,26 +673,34 @@ __global__ __launch_bounds__(256, 4) void k_hemv(const f4v* __restrict__ kp, con
             qi[e][r] = make_float2((float)q.x, (float)q.y);
         }
     }
-    if (active) {
-        const int col = J * kHemvTile + 64 * h + L;
-#pragma unroll
-        for (int r = 0; r < NRHS; ++r) {
-            const double2 q = col < Nc ? qbar[(int64_t)col * NRHS + r] : make_double2(0.0, 0.0);
-            qj[r * 64 + L] = make_float2((float)q.x, (float)q.y);
-            p2[r * 64 + L] = make_double2(0.0, 0.0);
-        }
-    }
-    __syncthreads();
     double d1[2][NRHS][2];
 #pragma unroll
     for (int e = 0; e < 2; ++e)
 #pragma unroll
         for (int r = 0; r < NRHS; ++r) d1[e][r][0] = d1[e][r][1] = 0.0;
-    if (active) {
-        if (offdiag)
-            hemv_half<NRHS, true>(kp, qj, p2, qi, d1, r2part, I, J, h, nbk, L);
-        else
-            hemv_half<NRHS, false>(kp, qj, p2, qi, d1, r2part, I, J, h, nbk, L);
+#pragma unroll 1
+    for (int k = 0; k < tpw; ++k) {
+        const int J = I + 2 * tpw * g + (wave >> 1) + 2 * k;
+        const bool active = J < nbk;   // wavefront-uniform
+        // q_J of the half's columns and cleared P2 sums in this wavefront's LDS (the
+        // barriers order them after the previous tile's reads; the trip count is uniform)
+        __syncthreads();
+        if (active) {
+            const int col = J * kHemvTile + 64 * h + L;
+#pragma unroll
+            for (int r = 0; r < NRHS; ++r) {
+                const double2 q = col < Nc ? qbar[(int64_t)col * NRHS + r] : make_double2(0.0, 0.0);
+                qj[r * 64 + L] = make_float2((float)q.x, (float)q.y);
+                p2[r * 64 + L] = make_double2(0.0, 0.0);
+            }
+        }
+        __syncthreads();
+        if (active) {
+            if (J != I)
+                hemv_half<NRHS, true>(kp, qj, p2, qi, d1, r2part, I, J, h, nbk, L);
+            else
+                hemv_half<NRHS, false>(kp, qj, p2, qi, d1, r2part, I, J, h, nbk, L);
+        }
     }
     // P1 partial of r_I: the 4 wavefronts' row sums added in LDS in a fixed order
     __syncthreads();
@@ -803,15 +818,13 @@ __device__ __forceinline__ void hemv_half64(const d2v* __restrict__ kp, const do
 template <int NRHS>
 __global__ __launch_bounds__(256, NRHS > 3 ? 2 : 4) void k_hemv64(const d2v* __restrict__ kp, const double2* __restrict__ qbar,
                                                    const int* __restrict__ table, double2* __restrict__ r1part,
-                                                   double2* __restrict__ r2part, int Nc, int nbk) {
+                                                   double2* __restrict__ r2part, int Nc, int nbk, int tpw) {
     extern __shared__ double2 hsm[];
     const int wave = threadIdx.x / kWave;
     const int L = threadIdx.x % kWave;
     const int code = table[blockIdx.x];
     const int I = code & 0xffff, g = code >> 16;
-    const int J = I + 2 * g + (wave >> 1);
     const int h = wave & 1;
-    const bool active = J < nbk;
     double2* qj = hsm + wave * NRHS * 64;   // q_J of the half's 64 columns
     double2 qi[2][NRHS];
 #pragma unroll
@@ -820,23 +833,29 @@ __global__ __launch_bounds__(256, NRHS > 3 ? 2 : 4) void k_hemv64(const d2v* __r
 #pragma unroll
         for (int r = 0; r < NRHS; ++r) qi[e][r] = row < Nc ? qbar[(int64_t)row * NRHS + r] : make_double2(0.0, 0.0);
     }
-    if (active) {
-        const int col = J * kHemvTile + 64 * h + L;
-#pragma unroll
-        for (int r = 0; r < NRHS; ++r)
-            qj[r * 64 + L] = col < Nc ? qbar[(int64_t)col * NRHS + r] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
     double d1[2][NRHS][2];
 #pragma unroll
     for (int e = 0; e < 2; ++e)
 #pragma unroll
         for (int r = 0; r < NRHS; ++r) d1[e][r][0] = d1[e][r][1] = 0.0;
-    if (active) {
-        if (J != I)
-            hemv_half64<NRHS, true>(kp, qj, qi, d1, r2part, I, J, h, nbk, L);
-        else
-            hemv_half64<NRHS, false>(kp, qj, qi, d1, r2part, I, J, h, nbk, L);
+#pragma unroll 1
+    for (int k = 0; k < tpw; ++k) {
+        const int J = I + 2 * tpw * g + (wave >> 1) + 2 * k;
+        const bool active = J < nbk;   // wavefront-uniform
+        __syncthreads();
+        if (active) {
+            const int col = J * kHemvTile + 64 * h + L;
+#pragma unroll
+            for (int r = 0; r < NRHS; ++r)
+                qj[r * 64 + L] = col < Nc ? qbar[(int64_t)col * NRHS + r] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        if (active) {
+            if (J != I)
+                hemv_half64<NRHS, true>(kp, qj, qi, d1, r2part, I, J, h, nbk, L);
+            else
+                hemv_half64<NRHS, false>(kp, qj, qi, d1, r2part, I, J, h, nbk, L);
+        }
     }
     __syncthreads();
     double2* red = hsm;   // [4][128][NRHS]
@@ -902,9 +921,14 @@ HemvShape hemv_shape(int64_t Nc, int dtype) {
     HemvShape h;
     h.nbk = (int)((Nc + kHemvTile - 1) / kHemvTile);
     h.tiles = (int64_t)h.nbk * (h.nbk + 1) / 2;
-    int64_t b = 0;
-    for (int I = 0; I < h.nbk; ++I) b += (h.nbk - I + 1) / 2;
-    h.blocks = b;
+    auto blocks = [&](int tpw) {
+        int64_t b = 0;
+        for (int I = 0; I < h.nbk; ++I) b += hemv_groups(h.nbk, I, tpw);
+        return b;
+    };
+    h.tpw = 1;
+    while (blocks(h.tpw) > kHemvBlocks && 2 * h.tpw < h.nbk) ++h.tpw;
+    h.blocks = blocks(h.tpw);
     h.elem_bytes = dtype == BSE_F64 ? sizeof(double2) : sizeof(float2);
     h.tile_bytes = (size_t)kHemvTile * kHemvTile * h.elem_bytes;
     return h;
@@ -924,7 +948,7 @@ hipError_t launch_hemv_pack(const Plan& p, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_hemv_table, dim3(1), dim3(kWave), 0, s, reinterpret_cast<int*>(p.ws + p.L.htab),
-                       reinterpret_cast<int*>(p.ws + p.L.htab) + h.blocks, h.nbk);
+                       reinterpret_cast<int*>(p.ws + p.L.htab) + h.blocks, h.nbk, h.tpw);
     return hipGetLastError();
 }
 
@@ -944,7 +968,8 @@ static hipError_t hemv_t(Plan& p, hipStream_t s) {
         // q_J of 4 wavefronts x 64 columns, or the P1 sums of 4 x 128 rows
         const size_t lds = (size_t)4 * kHemvTile * NRHS * sizeof(double2);
         hipLaunchKernelGGL((k_hemv64<NRHS>), dim3((unsigned)h.blocks), dim3(kBlock), lds, s,
-                           reinterpret_cast<const d2v*>(p.ws + p.L.kp), qbar, tab, r1, r2, (int)g.Nc, h.nbk);
+                           reinterpret_cast<const d2v*>(p.ws + p.L.kp), qbar, tab, r1, r2, (int)g.Nc, h.nbk,
+                           h.tpw);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_hemv_reduce<NRHS, double2>), rgrid, dim3(kBlock), 0, s, r1, r2, tab + h.blocks, rvec,
@@ -957,7 +982,7 @@ static hipError_t hemv_t(Plan& p, hipStream_t s) {
     const size_t lds = std::max((size_t)4 * NRHS * 64 * (sizeof(float2) + sizeof(double2)),
                                 (size_t)4 * kHemvTile * NRHS * sizeof(double2));
     hipLaunchKernelGGL((k_hemv<NRHS>), dim3((unsigned)h.blocks), dim3(kBlock), lds, s,
-                       reinterpret_cast<const f4v*>(p.ws + p.L.kp), qbar, tab, r1, r2, (int)g.Nc, h.nbk);
+                       reinterpret_cast<const f4v*>(p.ws + p.L.kp), qbar, tab, r1, r2, (int)g.Nc, h.nbk, h.tpw);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_hemv_reduce<NRHS, float2>), rgrid, dim3(kBlock), 0, s, r1, r2, tab + h.blocks, rvec,
