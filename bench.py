@@ -78,6 +78,8 @@ def _args():
                    help="FP32 coarse kernel: stream the whole K_c instead of the packed Hermitian tiles")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-race", action="store_true", help="skip the converged time-to-eps2 comparison")
+    p.add_argument("--race-eta", type=float, default=None,
+                   help="broadening (eV) of the converged time-to-eps2 comparison (default: the workload's)")
     p.add_argument("--cpu-steps", type=int, default=8, help="oracle steps timed for the CPU baseline")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 1 GiB device copy (for HBM counter calibration)")
@@ -218,7 +220,7 @@ def main():
     # ---- time to a converged eps2 at the workload's broadening, FP32 and BF16 forms
     race = None
     if args.config == "c1" and dtype == "f32" and args.m3 is None and not args.no_race:
-        race = converged_race(bs, cfg, P, prob)
+        race = converged_race(bs, cfg, P, prob, eta=args.race_eta)
 
     # ---- time to eps2 on the host from a ready plan (chain + continued fraction + copy)
     om = cfg.omega()
@@ -542,7 +544,7 @@ def spectrum_race(args):
     print(json.dumps(out), flush=True)
 
 
-def converged_race(bs, cfg, P, prob_f32, tol=1e-3, ref_steps=1800, check_every=20, cap=3000):
+def converged_race(bs, cfg, P, prob_f32, tol=1e-3, ref_steps=1800, check_every=20, cap=3000, eta=None):
     """Time to a converged eps2 at the workload's broadening (Sec. 2 after Eq. fraccont:
     chains run until the spectrum stops changing), from a ready plan to eps on the host,
     for the plain FP32 form and the BF16 coarse kernel, with bse_haydock_converge (a check
@@ -555,7 +557,8 @@ def converged_race(bs, cfg, P, prob_f32, tol=1e-3, ref_steps=1800, check_every=2
 
     from paper_1602_01863_amd import bse
 
-    om, C, eta = cfg.omega(), cfg.prefactor(), cfg.eta
+    om, C = cfg.omega(), cfg.prefactor()
+    eta = cfg.eta if eta is None else eta
     p64 = bse.problem_from_bands(bs, cfg, dtype="f64", max_rhs=cfg.n_pol)
     ch = p64.haydock(P, ref_steps)
     ref = p64.continued_fraction(ch, C, om, eta).cpu().numpy().imag
@@ -565,22 +568,31 @@ def converged_race(bs, cfg, P, prob_f32, tol=1e-3, ref_steps=1800, check_every=2
     out = {"eta_eV": eta, "tolerance": 1e-3, "stop_rule": f"max change <= {tol} x peak, checked every "
            f"{check_every} steps", "reference": f"FP64 chain of {ref_steps} steps", "forms": {}}
     probs = {"f32": prob_f32, "bf16": bse.problem_from_bands(bs, cfg, dtype="bf16", max_rhs=cfg.n_pol)}
-    for name, prob in probs.items():
-        prob.haydock_converge(P, cap, om, eta, C, tol, check_every)   # warm
+    # "_closed": every checked fraction closed by the constant chain of the chain's last 16
+    # coefficients (the square-root terminator), so the stop rule sees the closed spectrum
+    runs = [("f32", "f32", 0), ("bf16", "bf16", 0), ("f32_closed", "f32", 16), ("bf16_closed", "bf16", 16)]
+    for name, pk, closure in runs:
+        prob = probs[pk]
+        prob.haydock_converge(P, cap, om, eta, C, tol, check_every, closure=closure)   # warm
         best = None
         for _ in range(2):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            chc, eps = prob.haydock_converge(P, cap, om, eta, C, tol, check_every)
+            chc, eps = prob.haydock_converge(P, cap, om, eta, C, tol, check_every, closure=closure)
             e2 = eps.cpu().numpy().imag
             dt = time.perf_counter() - t0
             best = dt if best is None else min(best, dt)
         err = max(float(np.linalg.norm(e2[r] - ref[r]) / np.linalg.norm(ref[r])) for r in range(cfg.n_pol))
         out["forms"][name] = {"seconds": round(best, 4), "steps": chc["steps"].cpu().numpy().tolist(),
                               "eps2_rel_err": float("%.3g" % err), "within": bool(err <= 1e-3)}
+    prob_f32.haydock_converge(P, 1, om, eta, C, tol, check_every, closure=0)   # leave the plan as it was
     probs["bf16"].close()
-    f32, b16 = out["forms"]["f32"], out["forms"]["bf16"]
-    out["bf16_speedup_vs_f32"] = round(f32["seconds"] / b16["seconds"], 3)
+    f = out["forms"]
+    out["bf16_speedup_vs_f32"] = round(f["f32"]["seconds"] / f["bf16"]["seconds"], 3)
+    out["closure_speedup_f32"] = round(f["f32"]["seconds"] / f["f32_closed"]["seconds"], 3)
+    fastest = min((v["seconds"], k) for k, v in f.items() if v["within"])
+    out["fastest_within"] = {"form": fastest[1], "seconds": fastest[0],
+                             "speedup_vs_f32": round(f["f32"]["seconds"] / fastest[0], 3)}
     return out
 
 

@@ -176,9 +176,9 @@ bse_status bse_build_coarse_kernel(const bse_dims* dims, const double* vecs_coar
  *              Besides scratch space it holds the restrict tiles: a copy of d
  *              re-ordered for the restrict kernel, with the valence blocks already
  *              multiplied by the prefactors f (Sec. 3); for BSE_BF16_KC and
- *              BSE_F16_KC also the block-scaled copy of Kc, and for BSE_F32 and
- *              BSE_F32_VEC64 the packed copy of its 128 x 128 tiles on and above the
- *              diagonal (Kc itself is then not read after plan creation unless
+ *              BSE_F16_KC also the block-scaled copy of Kc, and for BSE_F32,
+ *              BSE_F32_VEC64 and BSE_F64 the packed copy of its 128 x 128 tiles on and
+ *              above the diagonal (Kc itself is then not read after plan creation unless
  *              bse_plan_set_coarse_product selects the full stream).
  *   stream     the copies are written by kernels enqueued on this stream; later
  *              calls on the plan must be ordered after them (same stream, or
@@ -227,6 +227,8 @@ bse_status bse_haydock_run(bse_plan* plan, const double* P, int32_t n_rhs, int32
  * max_omega |eps2 - eps2_previous| <= tol max_omega |eps2| (the paper gives 1% without a
  * denominator; here the change is measured against the spectrum's largest value), or
  * after max_steps steps.  Breakdown and zero start end a chain as in bse_haydock_run.
+ * The fraction of each check is truncated after a_m (Eq. fraccont) unless
+ * bse_plan_set_converge_closure selects the constant-chain closure.
  *   P, a, b, pnorm2, steps_done, status   as bse_haydock_run with n_steps = max_steps
  *                                          (lda = max_steps, ldb = max_steps + 1)
  *   omega      device FP64 [n_omega]
@@ -402,13 +404,24 @@ bse_status bse_plan_set_m3_band(bse_plan* plan, void* band, double w);
 /* Tunables of the coarse product: column splits (0 = automatic).  For sweeps. */
 bse_status bse_plan_set_gemv_splits(bse_plan* plan, int32_t n_split);
 
-/* Coarse product of Eq. (matmul2) for the FP32 coarse kernel (BSE_F32, BSE_F32_VEC64):
- * form 0 (default) reads the plan's packed copy of the tiles on and above the diagonal
- * (K_c is Hermitian, Eqs. bse1-bse2: half the bytes), with FP32 products and FP32 sums
- * over runs of 16 tile columns (32 rows for the conjugate-transposed tiles) added in
- * FP64; form 1 streams the whole Kc with FP64 products and sums.  Ignored by the other
- * precisions.  For comparisons and sweeps. */
+/* Coarse product of Eq. (matmul2) for the FP32 and FP64 coarse kernels (BSE_F32,
+ * BSE_F32_VEC64, BSE_F64): form 0 (default) reads the plan's packed copy of the tiles on
+ * and above the diagonal (K_c is Hermitian, Eqs. bse1-bse2: half the bytes); for FP32
+ * with FP32 products and FP32 sums over runs of 16 tile columns (32 rows for the
+ * conjugate-transposed tiles) added in FP64, for FP64 in FP64 throughout.  Form 1 streams
+ * the whole Kc with FP64 products and sums.  Ignored by the block-scaled forms.  For
+ * comparisons and sweeps. */
 bse_status bse_plan_set_coarse_product(bse_plan* plan, int32_t form);
+
+/* Tail of the continued fraction in bse_haydock_converge.  k = 0 (default): truncated
+ * after a_m, as Eq. (fraccont) is written.  1 <= k <= 64: closed beyond a_m by a chain
+ * with constant coefficients a_inf = mean(a_{m-k+1} .. a_m), b_inf = mean(b_{m-k+2} ..
+ * b_{m+1}) of the chain's own last k steps, whose resolvent is the root of
+ * b_inf^2 g^2 - (z - a_inf) g + 1 = 0 with Im g <= 0 (the standard square-root closure
+ * of a Lanczos fraction; the paper leaves the tail open): t_m = z - a_m - b_{m+1}^2 g.
+ * Both the stop rule and the returned spectrum then use the closed fraction; a check
+ * with m < k uses the truncated one.  BSE_ERR_INVALID_ARG for other k. */
+bse_status bse_plan_set_converge_closure(bse_plan* plan, int32_t k);
 
 /* Tunable of the restrict (Eq. matmul1): right-hand sides handled by one block, 1
  * (default) or 3 (used only when a call has exactly three right-hand sides).  Both

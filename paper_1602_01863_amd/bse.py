@@ -39,7 +39,8 @@ EXPORTED = [
     "bse_overlaps_bytes", "bse_build_overlaps", "bse_build_transition_energies",
     "bse_build_coarse_kernel", "bse_plan_create", "bse_plan_destroy", "bse_interp_matvec",
     "bse_haydock_run", "bse_haydock_converge", "bse_continued_fraction", "bse_plan_set_timing", "bse_plan_get_timing",
-    "bse_plan_set_gemv_splits", "bse_plan_set_coarse_product", "bse_plan_set_restrict_group", "bse_batch_create", "bse_batch_launch",
+    "bse_plan_set_gemv_splits", "bse_plan_set_coarse_product", "bse_plan_set_converge_closure",
+    "bse_plan_set_restrict_group", "bse_batch_create", "bse_batch_launch",
     "bse_batch_destroy", "bse_dense_forward", "bse_dense_backward", "bse_dense_backward_noalloc", "bse_mse_loss", "bse_adam_step",
     "bse_to_bf16", "bse_dense_forward_bf16", "bse_continued_fraction_terminated",
     "bse_build_divergence_coefficient", "bse_m3_band_info", "bse_build_m3_band", "bse_plan_set_m3_band",
@@ -89,6 +90,7 @@ def _load():
         "bse_plan_get_timing": (i32, [vp, P(dbl), P(i64)]),
         "bse_plan_set_gemv_splits": (i32, [vp, i32]),
         "bse_plan_set_coarse_product": (i32, [vp, i32]),
+        "bse_plan_set_converge_closure": (i32, [vp, i32]),
         "bse_plan_set_restrict_group": (i32, [vp, i32]),
         "bse_batch_create": (i32, [P(vp), i32, P(vp), P(i32), i32, P(vp), P(vp), P(vp), P(vp), P(vp), i32, P(vp)]),
         "bse_batch_launch": (i32, [vp, vp]),
@@ -230,8 +232,14 @@ def bse_plan_set_gemv_splits(plan, n_split: int):
 
 
 def bse_plan_set_coarse_product(plan, form: int):
-    """0: packed Hermitian tiles (default for the FP32 coarse kernel); 1: full stream."""
+    """0: packed Hermitian tiles (default for the FP32 and FP64 coarse kernels); 1: full stream."""
     _check(_lib.bse_plan_set_coarse_product(plan, int(form)), "bse_plan_set_coarse_product")
+
+
+def bse_plan_set_converge_closure(plan, k: int):
+    """Tail of the fraction in bse_haydock_converge: 0 truncated; k: constant chain of the
+    means of the last k coefficients."""
+    _check(_lib.bse_plan_set_converge_closure(plan, int(k)), "bse_plan_set_converge_closure")
 
 
 def bse_plan_set_restrict_group(plan, rhs_per_block: int):
@@ -490,9 +498,12 @@ class BSEProblem:
         return dict(a=a, b=b, pnorm2=pn, steps=steps, status=status)
 
     def haydock_converge(self, P, max_steps: int, omega, eta: float, prefactor: float, tol: float,
-                         check_every: int = 20):
+                         check_every: int = 20, closure: int = 0):
         """Chains run until eps2 changes by at most tol (relative to its peak) between
-        checks every check_every steps: (chain dict as haydock, eps [n_rhs, n_omega])."""
+        checks every check_every steps: (chain dict as haydock, eps [n_rhs, n_omega]).
+        closure = k > 0 closes each checked fraction by the constant chain of the means of
+        the chain's last k coefficients (0: truncated)."""
+        bse_plan_set_converge_closure(self.plan, closure)
         P = torch.as_tensor(P)
         if P.dim() == 1:
             P = P[None]

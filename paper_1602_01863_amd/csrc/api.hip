@@ -256,8 +256,9 @@ hipError_t enqueue_haydock(Plan& p, const double* P, int n_rhs, int n_steps, dou
 __global__ __launch_bounds__(1024) void k_converge_check(const double* __restrict__ a, const double* __restrict__ b,
                                                          int lda, int ldb, ChainState* __restrict__ cs, double prefactor,
                                                          const double* __restrict__ omega, int n_omega, double eta,
-                                                         double tol, int first, double* __restrict__ eps_re,
-                                                         double* __restrict__ eps_im, int32_t* __restrict__ active_out) {
+                                                         double tol, int first, int closure,
+                                                         double* __restrict__ eps_re, double* __restrict__ eps_im,
+                                                         int32_t* __restrict__ active_out) {
     __shared__ double sred[2][1024 / kWave];
     const int r = blockIdx.x;
     const ChainState st = cs[r];
@@ -265,12 +266,30 @@ __global__ __launch_bounds__(1024) void k_converge_check(const double* __restric
     const double pn = st.pnorm2;
     const double* ac = a + (int64_t)r * lda;
     const double* bc = b + (int64_t)r * ldb;
+    // the constant chain that closes the fraction: means of the last `closure` steps
+    const bool closed = closure > 0 && m >= closure;
+    double a_inf = 0.0, b_inf = 0.0, bm2 = 0.0;
+    if (closed) {
+        for (int j = m - closure; j < m; ++j) {
+            a_inf += ac[j];
+            b_inf += bc[j + 1];
+        }
+        a_inf /= closure;
+        b_inf /= closure;
+        bm2 = bc[m] * bc[m];   // b_{m+1}: 0 after a breakdown, which leaves the fraction exact
+    }
     double dmax = 0.0, emax = 0.0;
     for (int w = threadIdx.x; w < n_omega; w += blockDim.x) {
         double er = 1.0, ei = 0.0;
         if (m > 0 && pn != 0.0) {
             const double zr = omega[w], zi = eta;
             double tr = zr - ac[m - 1], ti = zi;
+            if (closed) {   // t_m = z - a_m - b_{m+1}^2 g_inf(z)
+                double gr, gi;
+                constant_chain(zr, zi, a_inf, b_inf, gr, gi);
+                tr -= bm2 * gr;
+                ti -= bm2 * gi;
+            }
             for (int j = m - 2; j >= 0; --j) {
                 const double b2 = bc[j + 1] * bc[j + 1];
                 const double den = tr * tr + ti * ti;
@@ -423,6 +442,7 @@ bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d, 
     p->ws = static_cast<char*>(workspace);
     p->n_split = 0;
     p->product_form = 0;
+    p->converge_closure = 0;
     p->side = nullptr;
     p->chk[0] = p->chk[1] = nullptr;
     p->restrict_group = 1;
@@ -536,7 +556,7 @@ bse_status bse_haydock_converge(bse_plan* plan, const double* P, int32_t n_rhs, 
         if (e != hipSuccess) break;
         ChainState* cs = reinterpret_cast<ChainState*>(p.ws + p.L.chain) + state_in(i) * kMaxRhs;
         hipLaunchKernelGGL(k_converge_check, dim3(n_rhs), dim3(1024), 0, stream, a, b, lda, ldb, cs, prefactor, omega,
-                           n_omega, eta, tol, c == 0 ? 1 : 0, eps_re, eps_im, flags);
+                           n_omega, eta, tol, c == 0 ? 1 : 0, p.converge_closure, eps_re, eps_im, flags);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipEventRecord(p.chk[c & 1], stream);
         // the previous check is read while this chunk runs: at most one chunk past the
@@ -644,6 +664,15 @@ bse_status bse_plan_set_coarse_product(bse_plan* plan, int32_t form) {
         return BSE_ERR_INVALID_ARG;
     }
     reinterpret_cast<Plan*>(plan)->product_form = form;
+    return BSE_OK;
+}
+
+bse_status bse_plan_set_converge_closure(bse_plan* plan, int32_t k) {
+    if (!plan || k < 0 || k > 64) {
+        set_error("bse_plan_set_converge_closure: k must be in [0, 64]");
+        return BSE_ERR_INVALID_ARG;
+    }
+    reinterpret_cast<Plan*>(plan)->converge_closure = k;
     return BSE_OK;
 }
 

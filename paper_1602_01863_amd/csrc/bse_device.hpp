@@ -234,6 +234,32 @@ __device__ __forceinline__ int cell_of_corner(int k, int z, int n_c) {
     return (i1 * n_c + i2) * n_c + i3;
 }
 
+// resolvent of the constant chain (a_inf, b_inf): root of b^2 g^2 - (z - a) g + 1 = 0
+// with Im g <= 0 (vanishes as |z| grows)
+__device__ __forceinline__ void constant_chain(double zr, double zi, double a_inf, double b_inf, double& gr,
+                                               double& gi) {
+    const double xr = zr - a_inf, xi = zi;
+    if (b_inf == 0.0) {
+        const double den = xr * xr + xi * xi;
+        gr = xr / den;
+        gi = -xi / den;
+        return;
+    }
+    // w = x^2 - 4 b^2, s = sqrt(w) (principal)
+    const double wr = xr * xr - xi * xi - 4.0 * b_inf * b_inf, wi = 2.0 * xr * xi;
+    const double r = hypot(wr, wi);
+    double sr = sqrt(0.5 * (r + wr)), si = sqrt(0.5 * fmax(r - wr, 0.0));
+    if (wi < 0.0) si = -si;
+    const double inv = 1.0 / (2.0 * b_inf * b_inf);
+    double g1r = (xr - sr) * inv, g1i = (xi - si) * inv;
+    if (g1i > 0.0) {  // the other root
+        g1r = (xr + sr) * inv;
+        g1i = (xi + si) * inv;
+    }
+    gr = g1r;
+    gi = g1i;
+}
+
 // ---- wavefront reductions -------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

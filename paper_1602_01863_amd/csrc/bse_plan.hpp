@@ -130,9 +130,11 @@ struct Plan {
     const char* m3_band;  // caller's band buffer: offset table, then the blocks
     double2* m3_yb;       // band product [rhs][N] (FP64), the tail of the band buffer
     int m3_noff_pad;      // band offsets, padded to whole chunks
-    // chains run to convergence: a side stream for reading the check flags, two events
+    // chains run to convergence: a side stream for reading the check flags, two events,
+    // and the tail of the checked fraction (0 truncated, k: constant chain of the last k)
     hipStream_t side;
     hipEvent_t chk[2];
+    int converge_closure;
 };
 
 // launches implemented in hotpath.hip (return hipSuccess or the launch error)

@@ -86,3 +86,41 @@ def test_chains_stop_independently(bse):
                                    cfg.prefactor(), om, 0.5)
         assert rel_l2(eps[r].imag, e_m[0].imag) < 1e-12
     prob.close()
+
+
+def test_closed_convergence_matches_the_oracle_and_stops_no_later(bse):
+    """The same C0 chain with each checked fraction closed by the constant chain of its last
+    16 coefficients (bse_plan_set_converge_closure): the returned spectrum is the oracle's
+    closed fraction of the device's own coefficients (1e-12), the stop rule holds on the
+    closed spectra, it lies within 10 tol of the oracle's converged spectrum, and it stops
+    no later than the truncated run."""
+    cfg = ti.get_config("c0")
+    prob = bse.problem_from_bands(bands(cfg), cfg, dtype="f64", max_rhs=1)
+    P = bands(cfg).P_flat()[:1]
+    om = cfg.omega()
+    C = cfg.prefactor()
+    eta, tol, every, cap, k = 0.3, 1e-5, 10, 400, 16
+    ch0, _ = prob.haydock_converge(P, cap, om, eta, C, tol, check_every=every)
+    m0 = int(ch0["steps"][0])
+    ch, eps = prob.haydock_converge(P, cap, om, eta, C, tol, check_every=every, closure=k)
+    ch = _host(ch)
+    eps = eps.cpu().numpy()
+    m = int(ch["steps"][0])
+    assert ch["status"][0] == bse.BSE_OK and m % every == 0 and k <= m <= m0
+
+    def closed(mm):   # a check with fewer than k steps uses the truncated fraction
+        a, b = ch["a"][:, :mm], ch["b"][:, :mm + 1]
+        if mm < k:
+            return O.continued_fraction(a, b, ch["pnorm2"], C, om, eta)
+        return O.continued_fraction_terminated(a, b, ch["pnorm2"], C, om, eta, a[:, mm - k:mm].mean(axis=1),
+                                               b[:, mm - k + 1:mm + 1].mean(axis=1))
+
+    e_m, e_prev, e_prev2 = closed(m), closed(m - every), closed(m - 2 * every)
+    assert rel_l2(eps.imag, e_m.imag) < 1e-12 and rel_l2(eps.real - 1, e_m.real - 1) < 1e-12
+    assert np.abs(e_m.imag - e_prev.imag).max() <= tol * np.abs(e_m.imag).max()
+    assert np.abs(e_prev.imag - e_prev2.imag).max() > tol * np.abs(e_prev.imag).max()
+    op = oracle_operator(cfg)
+    och = O.haydock(op.apply, P, cap)
+    oeps = O.continued_fraction(och["a"], och["b"], och["pnorm2"], C, om, eta)
+    assert rel_l2(eps.imag, oeps.imag) < 10 * tol
+    prob.close()

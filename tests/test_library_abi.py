@@ -87,6 +87,8 @@ def test_other_entry_points_check_arguments(bse):
     assert lib.bse_build_coarse_kernel(ctypes.byref(d_big), 1, 1, ctypes.byref(m), 1, None) == bse.BSE_ERR_UNSUPPORTED
     assert lib.bse_plan_set_gemv_splits(None, 4) == bse.BSE_ERR_INVALID_ARG
     assert lib.bse_plan_set_restrict_group(None, 1) == bse.BSE_ERR_INVALID_ARG
+    assert lib.bse_plan_set_coarse_product(None, 0) == bse.BSE_ERR_INVALID_ARG
+    assert lib.bse_plan_set_converge_closure(None, 16) == bse.BSE_ERR_INVALID_ARG
 
 
 def test_m3_band_geometry_and_checks(bse):
