@@ -181,9 +181,10 @@ def main():
     lowp = dtype in ("bf16", "f16")
     mat_bytes = {"f64": 16, "f32": 8, "f32v64": 8, "bf16": 4, "f16": 4}[dtype]
     nbk = -(-Nc // 64)
-    packed = dtype in ("f32", "f32v64", "f64") and not args.full_stream
+    packed = not args.full_stream
     if lowp:   # 64 x 64 blocks in the format (zero-padded) + one FP32 scale per block
-        kc_bytes = nbk * nbk * 64 * 64 * mat_bytes + nbk * nbk * 4
+        nblk = nbk * (nbk + 1) // 2 if packed else nbk * nbk   # packed: blocks on and above the diagonal
+        kc_bytes = nblk * 64 * 64 * mat_bytes + nblk * 4
     elif packed:   # the 128 x 128 tiles on and above the diagonal (K_c Hermitian)
         nt = -(-Nc // 128)
         kc_bytes = nt * (nt + 1) // 2 * 128 * 128 * mat_bytes
@@ -194,7 +195,10 @@ def main():
     achieved_gbs = gemv_bytes / (gemv_ms * 1e-3) / 1e9
     # matrix-core work actually issued: per 64 x 64 block and 16-row group, four 16x16x32
     # products (16 columns: 4 rhs x re/im x leading/remainder)
-    mfma_flops = (nbk * 4) * nbk * 4 * (2.0 * 16 * 16 * 32) if lowp else 0.0
+    # issued 16x16x32 products: 16 per stored block for P1, 16 more per off-diagonal block
+    # for P2 in the packed form (padding columns and the hi/lo split included)
+    mfma_flops = ((16 * nbk * nbk if not packed else 16 * nbk * (nbk + 1) // 2 + 16 * nbk * (nbk - 1) // 2)
+                  * (2.0 * 16 * 16 * 32)) if lowp else 0.0
 
     # ---- Method 3: the band product, timed the same way
     m3 = None
@@ -278,7 +282,9 @@ def main():
         "coarse_product": {
             "avg_ms": round(gemv_ms, 5), "launches": gemv_launches,
             "TFLOPs": round(gemv_flops / (gemv_ms * 1e-3) / 1e12, 3),
-            "engine": ("matrix cores 16x16x32 " + dtype + ", FP32 in-block accumulation (HBM-bound)") if lowp
+            "engine": ("matrix cores 16x16x32 " + dtype + ", FP32 in-block accumulation, blocks on and above the "
+                       "diagonal (HBM-bound)") if lowp and packed
+            else ("matrix cores 16x16x32 " + dtype + ", FP32 in-block accumulation (HBM-bound)") if lowp
             else ("VALU FP64 FMA on the packed Hermitian tiles (HBM-bound; no MFMA)") if packed and dtype == "f64"
             else ("VALU FP32 FMA on the packed Hermitian tiles, FP32 runs of 16 steps summed in FP64 "
                   "(HBM-bound; no MFMA)") if packed
@@ -287,7 +293,9 @@ def main():
             "MFMA_peak_TFLOPs": 2500.0 if lowp else None,
         },
         "roofline": {
-            "kernel": ("coarse product r = K_c qbar (k_gemv_mfma + k_gemv_reduce)" if lowp
+            "kernel": ("coarse product r = K_c qbar, packed Hermitian blocks (k_hemv_mfma + k_hm_reduce)"
+                       if lowp and packed
+                       else "coarse product r = K_c qbar (k_gemv_mfma + k_gemv_reduce)" if lowp
                        else "coarse product r = K_c qbar, packed Hermitian tiles (k_hemv64 + k_hemv_reduce)"
                        if packed and dtype == "f64"
                        else "coarse product r = K_c qbar, packed Hermitian tiles (k_hemv + k_hemv_reduce)"

@@ -409,8 +409,10 @@ bse_status bse_plan_set_gemv_splits(bse_plan* plan, int32_t n_split);
  * and above the diagonal (K_c is Hermitian, Eqs. bse1-bse2: half the bytes); for FP32
  * with FP32 products and FP32 sums over runs of 16 tile columns (32 rows for the
  * conjugate-transposed tiles) added in FP64, for FP64 in FP64 throughout.  Form 1 streams
- * the whole Kc with FP64 products and sums.  Ignored by the block-scaled forms.  For
- * comparisons and sweeps. */
+ * the whole Kc with FP64 products and sums.  For the block-scaled forms (BSE_BF16_KC,
+ * BSE_F16_KC) form 0 reads only the 64 x 64 blocks on and above the diagonal and forms
+ * both products on the matrix cores (the column product through a transposed LDS copy of
+ * each block), form 1 every block.  For comparisons and sweeps. */
 bse_status bse_plan_set_coarse_product(bse_plan* plan, int32_t form);
 
 /* Tail of the continued fraction in bse_haydock_converge.  k = 0 (default): truncated

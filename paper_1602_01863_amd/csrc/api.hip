@@ -131,7 +131,7 @@ Layout make_layout(const Geometry& g) {
     L.flags = take((size_t)kMaxRhs * sizeof(int32_t));
     L.vec_a = take((size_t)g.N * R * vec_elem_bytes(g.dtype));
     L.vec_b = take((size_t)g.N * R * vec_elem_bytes(g.dtype));
-    L.kq = L.kscale = L.qfrag = L.qsinv = off;
+    L.kq = L.kscale = L.qfrag = L.qsinv = L.mp1 = L.mp2 = L.mtab = off;
     L.kq_bytes = L.kscale_bytes = L.qfrag_bytes = 0;
     if (kc_lowp(g.dtype)) {
         const KqShape k = kq_shape(g.Nc);
@@ -142,6 +142,10 @@ Layout make_layout(const Geometry& g) {
         L.kscale = take(L.kscale_bytes);
         L.qfrag = take(L.qfrag_bytes);
         L.qsinv = take((size_t)k.nb * kMaxRhs * sizeof(float));
+        const HmShape hm = hm_shape(g.Nc);
+        L.mp1 = take((size_t)hm.runs * kKqBlock * R * sizeof(double2));
+        L.mp2 = take((size_t)(hm.upper - hm.nb) * kKqBlock * R * sizeof(float2));
+        L.mtab = take((size_t)(hm.runs + hm.nb + 1) * sizeof(int));
     }
     L.kp = L.hpart = L.htab = off;
     L.kp_bytes = 0;

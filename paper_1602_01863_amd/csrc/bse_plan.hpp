@@ -82,6 +82,15 @@ inline KqShape kq_shape(int64_t Nc) {
     return k;
 }
 inline bool kc_lowp(int dtype) { return dtype == BSE_BF16_KC || dtype == BSE_F16_KC; }
+// Packed Hermitian form of the block-scaled product (gemv.hip): runs of blocks (bi, bj),
+// bi <= bj, along block rows; one wavefront per run
+struct HmShape {
+    int nb;         // blocks per side
+    int run_len;    // blocks per run
+    int64_t runs;   // runs over all block rows
+    int64_t upper;  // blocks on and above the diagonal: nb (nb + 1) / 2
+};
+HmShape hm_shape(int64_t Nc);
 // Lanczos vectors in FP32 storage
 inline bool vec_is_f32(int dtype) { return dtype == BSE_F32 || kc_lowp(dtype); }
 
@@ -100,10 +109,11 @@ inline bool kc_packable(int dtype) { return dtype == BSE_F32 || dtype == BSE_F32
 
 // workspace regions (byte offsets from the workspace base); dsw_bytes == 0 when the
 // restrict reads the overlaps in their input layout; kq, kscale, qfrag, qsinv (the FP16
-// form's qbar scales) only for the low-precision forms; kp, hpart, htab only for the FP32 and FP64 coarse kernels
+// form's qbar scales) and mp1, mp2, mtab (partials and run table of their packed product)
+// only for the low-precision forms; kp, hpart, htab only for the FP32 and FP64 coarse kernels
 struct Layout {
     size_t qpart, qbar, rvec, gpart, ppart, rpart, chain, pend, flags, vec_a, vec_b, dsw, kq, kscale, qfrag, qsinv, kp,
-        hpart, htab;
+        hpart, htab, mp1, mp2, mtab;
     size_t dsw_bytes, kq_bytes, kscale_bytes, qfrag_bytes, kp_bytes;
     size_t total;
 };
@@ -159,6 +169,7 @@ hipError_t launch_quantize(const Plan& p, hipStream_t s);
 // packed Hermitian tiles and their block table (gemv.hip), at plan creation
 hipError_t launch_hemv_pack(const Plan& p, hipStream_t s);
 inline bool use_packed(const Plan& p) { return p.L.kp_bytes > 0 && p.product_form == 0; }
+inline bool use_packed_lowp(const Plan& p) { return kc_lowp(p.g.dtype) && p.product_form == 0; }
 // vector slice of a cell held in LDS by the tiled restrict: bytes, or 0 if it does not fit
 size_t restrict_tile_lds(const Geometry& g);
 

@@ -56,14 +56,16 @@ def lowp_bound(op, x, dtype):
       absolute floor of half the subnormal spacing over the group's scale: each 64-entry
       group of qbar is scaled by the power of two that puts its largest entry in
       [2^14, 2^15), so the floor is at most 2^-25 2^-14 max|qbar| <= 2^-39 max(|C||x|).
-    - FP32 accumulation of the 64 products of one block: 64 u32 per |term|.
+    - FP32 accumulation of the 64 products of one block: 64 u32 per |term|, plus 2 for the
+      packed Hermitian form's column products (the two conjugation terms are subtracted and
+      the leading and remainder parts added in FP32): 66.
     - the restrict's and prolong's FP32 contractions: FP32_INNER_UNITS u32.
     The kernel terms are bounded by |C|^H |K| |C| |x|.
     """
     aop = abs_operator(op)
     ax = np.abs(x)
     u = UNIT[dtype]
-    bound = product_bound(op, x, U32) + (u + 4 * u * u + (64 + FP32_INNER_UNITS) * U32) * np.abs(aop.apply_kernel(ax))
+    bound = product_bound(op, x, U32) + (u + 4 * u * u + (66 + FP32_INNER_UNITS) * U32) * np.abs(aop.apply_kernel(ax))
     if dtype == "f16":
         kmax = np.abs(op.Kc).max()
         colsum = np.abs(aop.restrict(ax)).sum(axis=1)                # 1^T |C||x| per rhs
@@ -74,15 +76,22 @@ def lowp_bound(op, x, dtype):
     return bound
 
 
+@pytest.mark.parametrize("form", [0, 1], ids=["packed", "full"])
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])
 @pytest.mark.parametrize("cfg", CASES, ids=IDS)
-def test_matvec_lowp_within_format_bound(bse, cfg, dtype):
+def test_matvec_lowp_within_format_bound(bse, cfg, dtype, form):
+    """Both coarse-product forms of the block-scaled kernel: the blocks on and above the
+    diagonal with the column products on the matrix cores too (0, the default), or every
+    block (1).  The packed form is reproducible bit for bit."""
     op = oracle_operator(cfg)
     prob = _problem(bse, cfg, dtype)
+    bse.bse_plan_set_coarse_product(prob.plan, form)
     x = ti.random_vectors(op.N, cfg.n_pol, 301)
     x = x / np.linalg.norm(x, axis=1, keepdims=True)          # unit vectors, as in the chain
     xs = prob.vector(x)
-    y = prob.matvec(xs).cpu().numpy().astype(complex)
+    y = prob.matvec(xs)
+    assert torch.equal(y, prob.matvec(xs))
+    y = y.cpu().numpy().astype(complex)
     xr = xs.cpu().numpy().astype(complex)
     ref = op.apply(xr)
     assert np.all(np.isfinite(y))
