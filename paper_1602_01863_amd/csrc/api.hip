@@ -143,9 +143,9 @@ Layout make_layout(const Geometry& g) {
         L.qfrag = take(L.qfrag_bytes);
         L.qsinv = take((size_t)k.nb * kMaxRhs * sizeof(float));
         const HmShape hm = hm_shape(g.Nc);
-        L.mp1 = take((size_t)hm.runs * kKqBlock * R * sizeof(double2));
-        L.mp2 = take((size_t)(hm.upper - hm.nb) * kKqBlock * R * sizeof(float2));
-        L.mtab = take((size_t)(hm.runs + hm.nb + 1) * sizeof(int));
+        L.mp1 = take((size_t)hm.runs * 2 * kKqBlock * R * sizeof(double2));
+        L.mp2 = take((size_t)hm.p2 * kKqBlock * R * sizeof(float2));
+        L.mtab = take((size_t)(hm.runs + hm.bands + 1) * sizeof(int));
     }
     L.kp = L.hpart = L.htab = off;
     L.kp_bytes = 0;

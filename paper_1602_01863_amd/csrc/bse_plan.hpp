@@ -82,13 +82,14 @@ inline KqShape kq_shape(int64_t Nc) {
     return k;
 }
 inline bool kc_lowp(int dtype) { return dtype == BSE_BF16_KC || dtype == BSE_F16_KC; }
-// Packed Hermitian form of the block-scaled product (gemv.hip): runs of blocks (bi, bj),
-// bi <= bj, along block rows; one wavefront per run
+// Packed Hermitian form of the block-scaled product (gemv.hip): runs of block columns over
+// bands of two block rows, blocks (bi, bj) with bi <= bj only; one wavefront per run
 struct HmShape {
     int nb;         // blocks per side
-    int run_len;    // blocks per run
-    int64_t runs;   // runs over all block rows
-    int64_t upper;  // blocks on and above the diagonal: nb (nb + 1) / 2
+    int bands;      // bands of two block rows: ceil(nb / 2)
+    int run_len;    // block columns per run
+    int64_t runs;   // runs over all bands
+    int64_t p2;     // column partials: one per (band, column block) right of the band
 };
 HmShape hm_shape(int64_t Nc);
 // Lanczos vectors in FP32 storage

@@ -455,8 +455,8 @@ __global__ __launch_bounds__(256) void k_gemv_mfma(const u32x4* __restrict__ kq,
 // ---- packed Hermitian product on the matrix cores (block-scaled BF16/FP16 K_c) ---------
 //
 // K_c is Hermitian, so the blocks (bi, bj) with bi <= bj of the block-scaled layout hold
-// all of it; the others are never read.  A wavefront takes a run of such blocks along one
-// block row and, for each block,
+// all of it; the others are never read.  A wavefront takes a band of two block rows
+// (bi0 = 2 bp, bi1 = bi0 + 1) and a run of block columns bj, and for each stored block
 //   P1: r_bi += K_(bi,bj) q_bj     (the stored A fragments, as k_gemv_mfma, all 64 rows),
 //   P2: r_bj += K_(bi,bj)^H q_bi   (off-diagonal blocks; the diagonal block is P1's whole).
 // P2 contracts over the block's rows, so it needs the block as the B operand with k = row:
@@ -467,25 +467,30 @@ __global__ __launch_bounds__(256) void k_gemv_mfma(const u32x4* __restrict__ kq,
 // transpose).  Conjugation: with the variants [qr, qi] (V1) and [-qi, qr] (V2) of q,
 //   Re r2 = sum Kr qr + Ki qi = (V1 Kr - V2 Ki) on the qr rows,  Im r2 = the same on the qi rows.
 // A block's FP32 product times its scale (a power of two, as is the FP16 q scale) is exact
-// in FP32: P1 is summed over the run in FP64 and written once per run, P2 is written per
-// off-diagonal block in FP32, and k_hm_reduce adds both kinds in a fixed order.
+// in FP32.  P1 is summed over the run in FP64 and written once per run and row; the P2 of
+// the band's two blocks in a column are added in FP32 and written once per (band, column);
+// k_hm_reduce adds both kinds in a fixed order.
 
 constexpr int kHmPitch = 72;     // bf16 per row of a transposed LDS plane (16-byte rows, spread banks)
 constexpr int kHmWaves = 2048;   // wavefronts the runs aim at: one round at 2 waves per SIMD
 constexpr int kHmBlock = 128;    // 2 independent wavefronts per workgroup: 36 KiB of LDS planes
 
-// column partials of the off-diagonal blocks (bi < bj), stored by column block: those of
-// column block bj are contiguous
-__host__ __device__ inline int64_t hm_p2_index(int bi, int bj) { return (int64_t)bj * (bj - 1) / 2 + bi; }
-__host__ __device__ inline int hm_runs_in_row(int nb, int bi, int len) { return (nb - bi + len - 1) / len; }
+// column partials: one per (band bp, column block bj) with 2 bp < bj, stored by column block
+// (those of column bj are contiguous; column bj has ceil(bj / 2) of them)
+__host__ __device__ inline int64_t hm_p2_index(int bp, int bj) {
+    const int64_t m = bj / 2;
+    return m * (m + (bj & 1)) + bp;
+}
+__host__ __device__ inline int hm_runs_in_band(int nb, int bp, int len) { return (nb - 2 * bp + len - 1) / len; }
 
 HmShape hm_shape(int64_t Nc) {
     HmShape h;
     h.nb = kq_shape(Nc).nb;
-    h.upper = (int64_t)h.nb * (h.nb + 1) / 2;
+    h.bands = (h.nb + 1) / 2;
+    h.p2 = hm_p2_index(0, h.nb);
     auto runs = [&](int len) {
         int64_t r = 0;
-        for (int bi = 0; bi < h.nb; ++bi) r += hm_runs_in_row(h.nb, bi, len);
+        for (int bp = 0; bp < h.bands; ++bp) r += hm_runs_in_band(h.nb, bp, len);
         return r;
     };
     h.run_len = 1;
@@ -494,15 +499,16 @@ HmShape hm_shape(int64_t Nc) {
     return h;
 }
 
-// run -> bi | bj0 << 16, runs row by row; row0[bi] = first run of block row bi
-__global__ void k_hm_table(int* __restrict__ runs, int* __restrict__ row0, int nb, int len) {
+// run -> bp | bj0 << 16, runs band by band; band0[bp] = first run of band bp
+__global__ void k_hm_table(int* __restrict__ runs, int* __restrict__ band0, int nb, int len) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int r = 0;
-    for (int bi = 0; bi < nb; ++bi) {
-        row0[bi] = r;
-        for (int bj = bi; bj < nb; bj += len) runs[r++] = bi | (bj << 16);
+    const int bands = (nb + 1) / 2;
+    for (int bp = 0; bp < bands; ++bp) {
+        band0[bp] = r;
+        for (int bj = 2 * bp; bj < nb; bj += len) runs[r++] = bp | (bj << 16);
     }
-    row0[nb] = r;
+    band0[bands] = r;
 }
 
 template <int FMT>
@@ -516,137 +522,152 @@ __global__ __launch_bounds__(kHmBlock, 2) void k_hemv_mfma(const u32x4* __restri
     const int run = blockIdx.x * (kHmBlock / kWave) + wave;
     if (run >= nruns) return;   // wavefront-uniform; the kernel has no block barrier
     const int code = runs[run];
-    const int bi = code & 0xffff, bj0 = code >> 16;
+    const int bp = code & 0xffff, bj0 = code >> 16;
+    const int bi0 = 2 * bp;
+    const int nrow = (bi0 + 1 < nb) ? 2 : 1;
     const int bj1 = min(nb, bj0 + run_len);
     unsigned short* pre = hm_lds + (size_t)wave * 2 * 64 * kHmPitch;
     unsigned short* pim = pre + 64 * kHmPitch;
     const int n = lane % 16, g = lane / 16;
-    // q_bi as the A operands of P2: (step, variant)
-    u32x4 a2[2][2];
+    // q of the band's rows as the A operands of P2: (row, step, variant), and their FP16 scales
+    // (P2's output rows m = 4 g + e hold right-hand side e; P1's column n holds rhs n % 4)
+    u32x4 a2[2][2][2];
+    float qs2[2][4];
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks)
+    for (int rr = 0; rr < 2; ++rr) {
+        const int bi = min(bi0 + rr, nb - 1);
 #pragma unroll
-        for (int v = 0; v < 2; ++v) a2[ks][v] = qf[((int64_t)(2 * bi + ks) * 2 + v) * kWave + lane];
-    // P2's output rows m = 4 g + e hold right-hand side e; P1's column n holds rhs n % 4
-    float qs2[4];
+        for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) qs2[e] = Lowp<FMT>::grouped ? qsinv[(int64_t)bi * kMaxRhs + e] : 1.0f;
-    double acc[4][4];
+            for (int v = 0; v < 2; ++v) a2[rr][ks][v] = qf[((int64_t)(2 * bi + ks) * 2 + v) * kWave + lane];
 #pragma unroll
-    for (int rg = 0; rg < 4; ++rg)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc[rg][e] = 0.0;
-    // the next block's fragments are loaded while the current one is used
-    u32x4 an[16];
-    {
-        const u32x4* ab = kq + ((int64_t)bi * nb + bj0) * 16 * kWave + lane;
-#pragma unroll
-        for (int f = 0; f < 16; ++f) an[f] = __builtin_nontemporal_load(ab + f * kWave);
+        for (int e = 0; e < 4; ++e) qs2[rr][e] = Lowp<FMT>::grouped ? qsinv[(int64_t)bi * kMaxRhs + e] : 1.0f;
     }
+    double acc[2][4][4];
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[rr][rg][e] = 0.0;
 #pragma unroll 1
     for (int bj = bj0; bj < bj1; ++bj) {
-        u32x4 a[16], b[2][2];
-#pragma unroll
-        for (int f = 0; f < 16; ++f) a[f] = an[f];
-        if (bj + 1 < bj1) {   // wavefront-uniform
-            const u32x4* ab = kq + ((int64_t)bi * nb + bj + 1) * 16 * kWave + lane;
-#pragma unroll
-            for (int f = 0; f < 16; ++f) an[f] = __builtin_nontemporal_load(ab + f * kWave);
-        }
+        u32x4 b[2][2];
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
             for (int v = 0; v < 2; ++v) b[ks][v] = qf[((int64_t)(2 * bj + ks) * 2 + v) * kWave + lane];
-        const float sc = kscale[(int64_t)bi * nb + bj];
         const float q1 = Lowp<FMT>::grouped ? qsinv[(int64_t)bj * kMaxRhs + (n & 3)] : 1.0f;
-        __builtin_amdgcn_sched_barrier(0);
-        // P1: row group rg, fragments (rg, step, part) = a[(rg * 2 + ks) * 2 + part]
-        const double w1 = (double)sc * (double)q1;   // powers of two: exact
+        float p2v[4][4];
 #pragma unroll
-        for (int rg = 0; rg < 4; ++rg) {
-            f32x4 d = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int cg = 0; cg < 4; ++cg)
 #pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                d = Lowp<FMT>::mfma(a[(rg * 2 + ks) * 2 + 0], b[ks][0], d);
-                d = Lowp<FMT>::mfma(a[(rg * 2 + ks) * 2 + 1], b[ks][1], d);
+            for (int e = 0; e < 4; ++e) p2v[cg][e] = 0.0f;
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            const int bi = bi0 + rr;
+            if (rr >= nrow || bj < bi) continue;   // wavefront-uniform: no such row, or a block below the diagonal
+            const u32x4* ab = kq + ((int64_t)bi * nb + bj) * 16 * kWave + lane;
+            u32x4 a[16];
+#pragma unroll
+            for (int f = 0; f < 16; ++f) a[f] = __builtin_nontemporal_load(ab + f * kWave);
+            const float sc = kscale[(int64_t)bi * nb + bj];
+            __builtin_amdgcn_sched_barrier(0);
+            // P1: row group rg, fragments (rg, step, part) = a[(rg * 2 + ks) * 2 + part]
+            const double w1 = (double)sc * (double)q1;   // powers of two: exact
+#pragma unroll
+            for (int rg = 0; rg < 4; ++rg) {
+                f32x4 d = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    d = Lowp<FMT>::mfma(a[(rg * 2 + ks) * 2 + 0], b[ks][0], d);
+                    d = Lowp<FMT>::mfma(a[(rg * 2 + ks) * 2 + 1], b[ks][1], d);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[rr][rg][e] = fma(w1, (double)d[e], acc[rr][rg][e]);
             }
+            if (bj == bi) continue;   // wavefront-uniform: the diagonal block
+            // the block into LDS, transposed: fragment (rg, ks, part), entry e holds
+            // K_part[row 16 rg + n][col 32 ks + 8 g + e] -> plane[col][row]
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // the previous block's reads are done
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[rg][e] = fma(w1, (double)d[e], acc[rg][e]);
+            for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+                    for (int part = 0; part < 2; ++part) {
+                        const u32x4 v = a[(rg * 2 + ks) * 2 + part];
+                        unsigned short* pl = (part ? pim : pre) + (32 * ks + 8 * g) * kHmPitch + 16 * rg + n;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const unsigned int wv = v[e / 2];
+                            pl[e * kHmPitch] = (unsigned short)((e & 1) ? (wv >> 16) : (wv & 0xffffu));
+                        }
+                    }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // writes before the reads of other lanes
+            // P2 per column group cg: B[k = row][n = col] = plane[16 cg + n][32 ks + 8 g .. + 7]
+#pragma unroll
+            for (int cg = 0; cg < 4; ++cg) {
+                f32x4 da = {0.0f, 0.0f, 0.0f, 0.0f}, db = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    const int o = (16 * cg + n) * kHmPitch + 32 * ks + 8 * g;
+                    const u32x4 kre = *reinterpret_cast<const u32x4*>(pre + o);
+                    const u32x4 kim = *reinterpret_cast<const u32x4*>(pim + o);
+                    da = Lowp<FMT>::mfma(a2[rr][ks][0], kre, da);
+                    db = Lowp<FMT>::mfma(a2[rr][ks][1], kim, db);
+                }
+                // D2[m = 4 g + e][col]: g = 0 qr_hi, 1 qi_hi, 2 qr_lo, 3 qi_lo rows of rhs e;
+                // the lo rows (lanes g + 2) are added to the hi rows
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float v = (da[e] - db[e]) * (sc * qs2[rr][e]);
+                    v += __shfl_xor(v, 32, kWave);
+                    p2v[cg][e] += v;
+                }
+            }
         }
-        if (bj == bi) continue;   // wavefront-uniform
-        // the block into LDS, transposed: fragment (rg, ks, part), entry e holds
-        // K_part[row 16 rg + n][col 32 ks + 8 g + e] -> plane[col][row]
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // the previous block's reads are done
+        if (bj > bi0 && g < 2) {   // the band's column partial of bj
+            float* out = p2part + hm_p2_index(bp, bj) * kKqBlock * n_rhs * 2;
+#pragma unroll
+            for (int cg = 0; cg < 4; ++cg)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (e < n_rhs) out[((int64_t)(16 * cg + n) * n_rhs + e) * 2 + g] = p2v[cg][e];
+        }
+    }
+    // P1 partials of the run, one per row: column n holds (hi, lo) parts in n and n + 8; rows
+    // 4 (lane / 16) + e of row group rg
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+        double* out1 = p1part + ((int64_t)run * 2 + rr) * kKqBlock * n_rhs * 2;
 #pragma unroll
         for (int rg = 0; rg < 4; ++rg)
 #pragma unroll
-            for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-                for (int part = 0; part < 2; ++part) {
-                    const u32x4 v = a[(rg * 2 + ks) * 2 + part];
-                    unsigned short* pl = (part ? pim : pre) + (32 * ks + 8 * g) * kHmPitch + 16 * rg + n;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const unsigned int wv = v[e / 2];
-                        pl[e * kHmPitch] = (unsigned short)((e & 1) ? (wv >> 16) : (wv & 0xffffu));
-                    }
-                }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // writes before the reads of other lanes
-        // P2 per column group cg: B[k = row][n = col] = plane[16 cg + n][32 ks + 8 g .. + 7]
-        float* out = p2part + hm_p2_index(bi, bj) * kKqBlock * n_rhs * 2;
-#pragma unroll
-        for (int cg = 0; cg < 4; ++cg) {
-            f32x4 da = {0.0f, 0.0f, 0.0f, 0.0f}, db = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                const int o = (16 * cg + n) * kHmPitch + 32 * ks + 8 * g;
-                const u32x4 kre = *reinterpret_cast<const u32x4*>(pre + o);
-                const u32x4 kim = *reinterpret_cast<const u32x4*>(pim + o);
-                da = Lowp<FMT>::mfma(a2[ks][0], kre, da);
-                db = Lowp<FMT>::mfma(a2[ks][1], kim, db);
-            }
-            // D2[m = 4 g + e][col]: g = 0 qr_hi, 1 qi_hi, 2 qr_lo, 3 qi_lo rows of rhs e;
-            // the lo rows (lanes g + 2) are added to the hi rows
-            float v[4];
-#pragma unroll
             for (int e = 0; e < 4; ++e) {
-                v[e] = (da[e] - db[e]) * (sc * qs2[e]);
-                v[e] += __shfl_xor(v[e], 32, kWave);
+                const double v = acc[rr][rg][e] + __shfl_xor(acc[rr][rg][e], 8, kWave);
+                const int r = n & 3, comp = (n >> 2) & 1;
+                if (n < 8 && r < n_rhs) out1[((int64_t)(16 * rg + 4 * g + e) * n_rhs + r) * 2 + comp] = v;
             }
-            if (g < 2) {
-                const int col = 16 * cg + n;
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (e < n_rhs) out[((int64_t)col * n_rhs + e) * 2 + g] = v[e];
-            }
-        }
     }
-    // P1 partial of the run: column n holds (hi, lo) parts in n and n + 8; rows 4 (lane / 16) + e
-    double* out1 = p1part + (int64_t)run * kKqBlock * n_rhs * 2;
-#pragma unroll
-    for (int rg = 0; rg < 4; ++rg)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const double v = acc[rg][e] + __shfl_xor(acc[rg][e], 8, kWave);
-            const int r = n & 3, comp = (n >> 2) & 1;
-            if (n < 8 && r < n_rhs) out1[((int64_t)(16 * rg + 4 * g + e) * n_rhs + r) * 2 + comp] = v;
-        }
 }
 
-// r[i][rhs] = the P1 partials of the runs of block row b = i / 64 (in order), then the P2
-// partials of the blocks (0, b) .. (b - 1, b); eight lanes per output and a fixed butterfly
+// r[i][rhs] = the P1 partials of the runs of band b / 2 for row b = i / 64 (in order), then
+// the P2 partials of the bands bp with 2 bp < b; eight lanes per output and a fixed butterfly
 template <int NRHS>
 __global__ __launch_bounds__(256) void k_hm_reduce(const double2* __restrict__ p1, const float2* __restrict__ p2,
-                                                   const int* __restrict__ row0, double2* __restrict__ rout, int Nc) {
+                                                   const int* __restrict__ band0, double2* __restrict__ rout, int Nc) {
     constexpr int LN = 8;
     const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LN;
     const int k = threadIdx.x % LN;
     const int64_t oc = min(o, (int64_t)Nc * NRHS - 1);   // lanes past the end: same work, no store
     const int i = (int)(oc / NRHS), r = (int)(oc % NRHS);
     const int b = i / kKqBlock, w = i % kKqBlock;
-    const int r0 = row0[b], n1 = row0[b + 1] - r0;
-    const int n = n1 + b;
-    const float2* q2 = p2 + (hm_p2_index(0, b) * kKqBlock + w) * NRHS + r;   // P2 of (bi, b) at bi * 64 NRHS
+    const int bp = b / 2, rr = b & 1;
+    const int r0 = band0[bp], n1 = band0[bp + 1] - r0;
+    const int n = n1 + (b + 1) / 2;
+    const double2* q1 = p1 + (((int64_t)r0 * 2 + rr) * kKqBlock + w) * NRHS + r;   // run t at t 2 64 NRHS
+    const float2* q2 = p2 + (hm_p2_index(0, b) * kKqBlock + w) * NRHS + r;          // band t at t 64 NRHS
     double re = 0.0, im = 0.0;
     for (int t0 = k; t0 < n; t0 += 4 * LN) {
         double2 v[4];
@@ -654,7 +675,7 @@ __global__ __launch_bounds__(256) void k_hm_reduce(const double2* __restrict__ p
         for (int u = 0; u < 4; ++u) {
             const int t = min(t0 + u * LN, n - 1);
             if (t < n1) {
-                v[u] = p1[((int64_t)(r0 + t) * kKqBlock + w) * NRHS + r];
+                v[u] = q1[(int64_t)t * 2 * kKqBlock * NRHS];
             } else {
                 const float2 f = q2[(int64_t)(t - n1) * kKqBlock * NRHS];
                 v[u] = make_double2(f.x, f.y);
