@@ -53,7 +53,7 @@ typedef enum {
     BSE_ERR_INVALID_ARG = -1,
     BSE_ERR_HIP = -2,
     BSE_ERR_NONFINITE = -3,          /* chain status: a_i or b_{i+1} not finite */
-    BSE_ERR_UNSUPPORTED = -4,        /* band counts or precision not compiled in */
+    BSE_ERR_UNSUPPORTED = -4,        /* band counts or sizes outside what a call takes */
     BSE_ERR_WORKSPACE = -5           /* workspace missing, misaligned or too small */
 } bse_status;
 
@@ -183,6 +183,11 @@ bse_status bse_build_coarse_kernel(const bse_dims* dims, const double* vecs_coar
  *   stream     the copies are written by kernels enqueued on this stream; later
  *              calls on the plan must be ordered after them (same stream, or
  *              synchronised).
+ * Band counts: any nv, nc with nv + nc <= 16 and nv nc <= 32 (else BSE_ERR_UNSUPPORTED).
+ * The pairs (1,1) (1,2) (2,2) (2,3) (3,3) (3,4) (3,6) (4,6) run tuned kernels with the
+ * counts fixed at compile time; any other pair runs general kernels that take them at
+ * run time (FP64 arithmetic, slower) and has no Method 3 band (bse_plan_set_m3_band
+ * returns BSE_ERR_UNSUPPORTED for it).
  */
 bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d,
                            const double* delta, void* workspace, size_t workspace_bytes,

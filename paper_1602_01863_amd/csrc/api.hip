@@ -420,8 +420,8 @@ bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d, 
     *plan_out = nullptr;
     Geometry g;
     if (!make_geometry(dims, &g)) return BSE_ERR_INVALID_ARG;
-    if (!supported_bands(g.nv, g.nc)) {
-        set_error("bands nv=%d nc=%d are not compiled in", g.nv, g.nc);
+    if (!bands_in_range(g.nv, g.nc)) {
+        set_error("bands nv=%d nc=%d: the hot path takes nv + nc <= 16 and nv nc <= 32", g.nv, g.nc);
         return BSE_ERR_UNSUPPORTED;
     }
     if (!Kc || !d || !delta) {

@@ -194,6 +194,15 @@ hipError_t restrict_launch(const Plan& p, int mode, const void* x, const void* w
                            void* out, int step, double* a, double* b, int lda, int ldb, int n_rhs, hipStream_t s);
 template <class M2, class V2, int NV, int NC>
 hipError_t prolong_launch(const Plan& p, int mode, const void* x, void* out, int step, int n_rhs, hipStream_t s);
+// band pairs without a compiled form: nv, nc at run time (restrict.hip, prolong.hip)
+template <class M2, class V2>
+hipError_t restrict_any_launch(const Plan& p, int mode, const void* x, const void* w, const void* psi, const double* P,
+                               void* out, int step, double* a, double* b, int lda, int ldb, int n_rhs, hipStream_t s);
+template <class M2, class V2>
+hipError_t prolong_any_launch(const Plan& p, int mode, const void* x, void* out, int step, int n_rhs, hipStream_t s);
+// band counts the hot path takes: the compiled pairs at full speed, any other pair with
+// nv + nc <= 16 and nv nc <= 32 through the run-time forms
+inline bool bands_in_range(int nv, int nc) { return nv >= 1 && nc >= 1 && nv + nc <= 16 && nv * nc <= 32; }
 
 // chain-state copy read by the kernels of a step, written by its collapse
 __host__ __device__ inline int state_in(int step) { return step & 1; }

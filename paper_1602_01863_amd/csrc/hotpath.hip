@@ -168,7 +168,16 @@ hipError_t launch_restrict(const Plan& p, int mode, const void* x, const void* w
     if (nv == a_ && nc == b_) return restrict_dt<a_, b_>(p, mode, x, w, psi, P, out, step, a, b, lda, ldb, n_rhs, s);
     BSE_BANDS(BSE_CASE)
 #undef BSE_CASE
-    return hipErrorInvalidValue;
+    switch (p.g.dtype) {
+        case BSE_F64:
+            return restrict_any_launch<double2, double2>(p, mode, x, w, psi, P, out, step, a, b, lda, ldb, n_rhs, s);
+        case BSE_F32:
+        case BSE_BF16_KC:
+        case BSE_F16_KC:
+            return restrict_any_launch<float2, float2>(p, mode, x, w, psi, P, out, step, a, b, lda, ldb, n_rhs, s);
+        default:
+            return restrict_any_launch<float2, double2>(p, mode, x, w, psi, P, out, step, a, b, lda, ldb, n_rhs, s);
+    }
 }
 
 hipError_t launch_prolong(const Plan& p, int mode, const void* x, void* out, int step, int n_rhs, hipStream_t s) {
@@ -177,7 +186,13 @@ hipError_t launch_prolong(const Plan& p, int mode, const void* x, void* out, int
     if (nv == a_ && nc == b_) return prolong_dt<a_, b_>(p, mode, x, out, step, n_rhs, s);
     BSE_BANDS(BSE_CASE)
 #undef BSE_CASE
-    return hipErrorInvalidValue;
+    switch (p.g.dtype) {
+        case BSE_F64: return prolong_any_launch<double2, double2>(p, mode, x, out, step, n_rhs, s);
+        case BSE_F32:
+        case BSE_BF16_KC:
+        case BSE_F16_KC: return prolong_any_launch<float2, float2>(p, mode, x, out, step, n_rhs, s);
+        default: return prolong_any_launch<float2, double2>(p, mode, x, out, step, n_rhs, s);
+    }
 }
 
 hipError_t launch_collapse(const Plan& p, int mode, int step, double* b, int ldb, int n_rhs, hipStream_t s) {

@@ -488,4 +488,107 @@ hipError_t prolong_launch(const Plan& p, int mode, const void* x, void* out, int
     BSE_PROLONG_INST(float2, double2, A, B)
 BSE_BANDS(BSE_PROLONG_ALL)
 
+// ---- any band counts: nv and nc at run time ---------------------------------------------
+//
+// For band pairs without a compiled form.  One block per coarse cell; one thread per vector
+// entry (subpoint, v, c) of each right-hand side in turn forms
+//   w = delta psi_i + sum_z f(sub, z) sum_{n1} Dv[v][n1] sum_{n2} r_z[n1][n2] conj(Dc[c][n2])
+//       [- b_i psi_{i-1}] [+ s_i y]
+// in FP64 and, in a chain, the block's partials of <u_i|w> and ||w||^2.
+template <class M2, class V2, int MODE>
+__global__ __launch_bounds__(256) void k_prolong_any(const M2* __restrict__ d, const double* __restrict__ delta,
+                                                     const double2* __restrict__ rvec, const V2* __restrict__ x, V2* out,
+                                                     double* __restrict__ ppart, const ChainState* __restrict__ chain,
+                                                     int n_c, int n_div, int neighbours, int64_t N, int n_rhs,
+                                                     const double2* __restrict__ yb, int nv, int nc) {
+    __shared__ double sred[kBlock / kWave];
+    const int np = nv * nc, ne = nv * nv + nc * nc;
+    const int ndiv3 = n_div * n_div * n_div;
+    const int cell = blockIdx.x;
+    const int64_t kd0 = (int64_t)cell * ndiv3;
+    for (int rhs = 0; rhs < n_rhs; ++rhs) {   // uniform
+        double s_cur = 1.0, c_prev = 0.0;
+        if (MODE == PROLONG_LANCZOS) {
+            s_cur = chain[rhs].s_cur;                        // psi_i = s_i u_i
+            c_prev = chain[rhs].b_cur * chain[rhs].s_prev;   // b_i psi_{i-1} = b_i s_{i-1} u_{i-1}
+        }
+        const bool use_prev = (MODE == PROLONG_LANCZOS) && c_prev != 0.0;
+        double pw = 0.0, ww = 0.0;
+        for (int o = threadIdx.x; o < ndiv3 * np; o += blockDim.x) {
+            const int sub = o / np, pe = o % np, v = pe / nc, c = pe % nc;
+            const int64_t kd = kd0 + sub;
+            const int64_t t0 = (int64_t)rhs * N + kd * np + pe;
+            const cd xv = ld(x + t0);
+            cd acc = cscale(xv, delta[kd * np + pe] * s_cur);
+            if (use_prev) {
+                const cd pv = ld(out + t0);
+                acc.re = fma(-c_prev, pv.re, acc.re);
+                acc.im = fma(-c_prev, pv.im, acc.im);
+            }
+            if (yb) {   // Method 3 band product of u_i (uniform)
+                const double2 y = yb[t0];
+                acc.re = fma(s_cur, y.x, acc.re);
+                acc.im = fma(s_cur, y.y, acc.im);
+            }
+            for (int z = 0; z < 8; ++z) {
+                const double f = prefactor(sub, z, n_div, neighbours);
+                if (f == 0.0) continue;
+                const double2* rb = rvec + (int64_t)corner_index(cell, z, n_c) * np * n_rhs + rhs;
+                const M2* db = d + (int64_t)(cell * 8 + z) * ne * ndiv3 + sub;
+                cd y = cmake(0.0, 0.0);
+                for (int n1 = 0; n1 < nv; ++n1) {
+                    cd tt = cmake(0.0, 0.0);   // sum_n2 r[n1][n2] conj(Dc[c][n2])
+                    for (int n2 = 0; n2 < nc; ++n2) {
+                        const double2 r = rb[(int64_t)(n1 * nc + n2) * n_rhs];
+                        cfma_jc(tt, cmake(r.x, r.y), ld(db + (int64_t)(nv * nv + c * nc + n2) * ndiv3));
+                    }
+                    cfma(y, ld(db + (int64_t)(v * nv + n1) * ndiv3), tt);
+                }
+                acc.re = fma(f, y.re, acc.re);
+                acc.im = fma(f, y.im, acc.im);
+            }
+            st(out + t0, acc);
+            if (MODE == PROLONG_LANCZOS) {
+                const cd wr = rounded(acc, out);
+                pw = fma(xv.re, wr.re, pw);
+                pw = fma(xv.im, wr.im, pw);
+                ww = fma(wr.re, wr.re, ww);
+                ww = fma(wr.im, wr.im, ww);
+            }
+        }
+        if (MODE == PROLONG_LANCZOS) {
+            pw = block_sum(pw, sred);
+            ww = block_sum(ww, sred);
+            if (threadIdx.x == 0) {
+                ppart[((int64_t)cell * n_rhs + rhs) * 2] = pw;
+                ppart[((int64_t)cell * n_rhs + rhs) * 2 + 1] = ww;
+            }
+        }
+    }
+}
+
+template <class M2, class V2>
+hipError_t prolong_any_launch(const Plan& p, int mode, const void* x, void* out, int step, int n_rhs, hipStream_t s) {
+    const Geometry& g = p.g;
+    const double2* rvec = reinterpret_cast<const double2*>(p.ws + p.L.rvec);
+    double* ppart = reinterpret_cast<double*>(p.ws + p.L.ppart);
+    const ChainState* cs = reinterpret_cast<const ChainState*>(p.ws + p.L.chain) + state_in(step) * kMaxRhs;
+    const M2* d = reinterpret_cast<const M2*>(p.d);
+    const double2* yb = p.m3_band ? p.m3_yb : nullptr;
+    dim3 grid(g.ncells), block(kBlock);
+    if (mode == PROLONG_PLAIN)
+        hipLaunchKernelGGL((k_prolong_any<M2, V2, PROLONG_PLAIN>), grid, block, 0, s, d, p.delta, rvec,
+                           reinterpret_cast<const V2*>(x), reinterpret_cast<V2*>(out), ppart, cs, g.n_c, g.n_div,
+                           g.neighbours, g.N, n_rhs, yb, g.nv, g.nc);
+    else
+        hipLaunchKernelGGL((k_prolong_any<M2, V2, PROLONG_LANCZOS>), grid, block, 0, s, d, p.delta, rvec,
+                           reinterpret_cast<const V2*>(x), reinterpret_cast<V2*>(out), ppart, cs, g.n_c, g.n_div,
+                           g.neighbours, g.N, n_rhs, yb, g.nv, g.nc);
+    return hipGetLastError();
+}
+
+template hipError_t prolong_any_launch<double2, double2>(const Plan&, int, const void*, void*, int, int, hipStream_t);
+template hipError_t prolong_any_launch<float2, float2>(const Plan&, int, const void*, void*, int, int, hipStream_t);
+template hipError_t prolong_any_launch<float2, double2>(const Plan&, int, const void*, void*, int, int, hipStream_t);
+
 }  // namespace bse

@@ -34,6 +34,67 @@ __device__ __forceinline__ double xor_sum_j(double v) {
     return v;
 }
 
+// Chain prefix of the general restricts (one block per (cell, right-hand side)).  At the
+// chain start the coefficients are zeroed and u_1 = P; in an update
+// u_{i+1} = w - a_i psi_i = w - a_i s_i u_i (Eq. bi) with a_i = s_i sum_cells <u_i|w>_cell
+// (Eq. ai), summed from the prolong's per-cell partials by every block in the same fixed
+// order; the block of cell 0 records a_i.  The block writes its slice of u to out and adds
+// the slice's ||u||^2 (and ||P||^2 at the start) into uu and pp.
+template <class V2, int MODE>
+__device__ __forceinline__ void restrict_chain_prefix(const V2* x, const V2* __restrict__ psi,
+                                                      const double2* __restrict__ P, V2* out,
+                                                      const ChainState* __restrict__ cs,
+                                                      StepScalars* __restrict__ pend,
+                                                      const double* __restrict__ ppart, double* __restrict__ alpha,
+                                                      double* __restrict__ beta, int lda, int ldb, int step, int cell,
+                                                      int ncells, int rhs, int n_rhs, int64_t base, int nelem,
+                                                      double* sred, double& uu, double& pp) {
+    const int t = threadIdx.x;
+    if (MODE == RESTRICT_INIT) {
+        // chain coefficients start at zero
+        const int64_t tid = (int64_t)(cell * n_rhs + rhs) * blockDim.x + t;
+        const int64_t nth = (int64_t)ncells * n_rhs * blockDim.x;
+        for (int64_t i = tid; i < (int64_t)n_rhs * lda; i += nth) alpha[i] = 0.0;
+        for (int64_t i = tid; i < (int64_t)n_rhs * ldb; i += nth) beta[i] = 0.0;
+    }
+    double coef = 0.0;
+    bool ok = true;
+    if (MODE == RESTRICT_UPDATE) {
+        const double pw = block_sum_strided(ppart + rhs * 2, ncells, n_rhs * 2, sred);
+        const double ww = block_sum_strided(ppart + rhs * 2 + 1, ncells, n_rhs * 2, sred);
+        const ChainState st = cs[rhs];
+        const double a = st.s_cur * pw;
+        ok = st.active && isfinite(a) && isfinite(ww);
+        coef = ok ? a * st.s_cur : 0.0;
+        if (cell == 0 && t == 0 && st.active) {
+            StepScalars sc;
+            sc.a = a;
+            sc.ww = ww;
+            sc.ok = ok;
+            sc.pad[0] = sc.pad[1] = sc.pad[2] = 0;
+            pend[rhs] = sc;
+            if (ok) alpha[(int64_t)rhs * lda + step] = a;
+        }
+    }
+    for (int i = t; i < nelem; i += blockDim.x) {
+        cd u = cmake(0.0, 0.0);
+        if (MODE == RESTRICT_INIT) {
+            u = ld(P + base + i);
+            pp = fma(u.re, u.re, pp);
+            pp = fma(u.im, u.im, pp);
+        } else if (ok) {
+            u = ld(x + base + i);
+            const cd ps = ld(psi + base + i);
+            u.re = fma(-coef, ps.re, u.re);
+            u.im = fma(-coef, ps.im, u.im);
+        }
+        st(out + base + i, u);
+        const cd ur = rounded(u, out);
+        uu = fma(ur.re, ur.re, uu);
+        uu = fma(ur.im, ur.im, uu);
+    }
+}
+
 template <class M2, class V2, int NV, int NC, int MODE>
 __global__ __launch_bounds__(256, (NV * NC > 18) ? 2 : 3) void k_restrict2(
     const M2* __restrict__ d, const V2* x, const V2* __restrict__ psi, const double2* __restrict__ P, V2* out,
@@ -61,52 +122,9 @@ __global__ __launch_bounds__(256, (NV * NC > 18) ? 2 : 3) void k_restrict2(
     const int nelem = ndiv3 * NP;
     double uu = 0.0, pp = 0.0;
 
-    if (MODE == RESTRICT_INIT) {
-        // chain coefficients start at zero
-        const int64_t tid = (int64_t)(cell * n_rhs + rhs) * blockDim.x + t;
-        const int64_t nth = (int64_t)ncells * n_rhs * blockDim.x;
-        for (int64_t i = tid; i < (int64_t)n_rhs * lda; i += nth) alpha[i] = 0.0;
-        for (int64_t i = tid; i < (int64_t)n_rhs * ldb; i += nth) beta[i] = 0.0;
-    }
     if (MODE != RESTRICT_PLAIN) {
-        // init: u_1 = P.  update: u_{i+1} = w - a_i psi_i = w - a_i s_i u_i  (Eq. bi), with
-        // a_i = s_i sum_cells <u_i|w>_cell  (Eq. ai)
-        double coef = 0.0;
-        bool ok = true;
-        if (MODE == RESTRICT_UPDATE) {
-            const double pw = block_sum_strided(ppart + rhs * 2, ncells, n_rhs * 2, sred);
-            const double ww = block_sum_strided(ppart + rhs * 2 + 1, ncells, n_rhs * 2, sred);
-            const ChainState st = cs[rhs];
-            const double a = st.s_cur * pw;
-            ok = st.active && isfinite(a) && isfinite(ww);
-            coef = ok ? a * st.s_cur : 0.0;
-            if (cell == 0 && t == 0 && st.active) {
-                StepScalars sc;
-                sc.a = a;
-                sc.ww = ww;
-                sc.ok = ok;
-                sc.pad[0] = sc.pad[1] = sc.pad[2] = 0;
-                pend[rhs] = sc;
-                if (ok) alpha[(int64_t)rhs * lda + step] = a;
-            }
-        }
-        for (int i = t; i < nelem; i += blockDim.x) {
-            cd u = cmake(0.0, 0.0);
-            if (MODE == RESTRICT_INIT) {
-                u = ld(P + base + i);
-                pp = fma(u.re, u.re, pp);
-                pp = fma(u.im, u.im, pp);
-            } else if (ok) {
-                u = ld(x + base + i);
-                const cd ps = ld(psi + base + i);
-                u.re = fma(-coef, ps.re, u.re);
-                u.im = fma(-coef, ps.im, u.im);
-            }
-            st(out + base + i, u);
-            const cd ur = rounded(u, out);
-            uu = fma(ur.re, ur.re, uu);
-            uu = fma(ur.im, ur.im, uu);
-        }
+        restrict_chain_prefix<V2, MODE>(x, psi, P, out, cs, pend, ppart, alpha, beta, lda, ldb, step, cell, ncells, rhs,
+                                        n_rhs, base, nelem, sred, uu, pp);
         __syncthreads();  // the block's slice of u is visible to all its lanes
     }
     const V2* src = (MODE == RESTRICT_PLAIN) ? x : out;
@@ -688,5 +706,100 @@ hipError_t restrict_launch(const Plan& p, int mode, const void* x, const void* w
     BSE_RESTRICT_INST(float2, float2, A, B)     \
     BSE_RESTRICT_INST(float2, double2, A, B)
 BSE_BANDS(BSE_RESTRICT_ALL)
+
+// ---- any band counts: nv and nc at run time ---------------------------------------------
+//
+// For band pairs without a compiled form.  One block per (cell, right-hand side): the chain
+// prefix as above, then one thread per restricted entry (corner z, n3, n4) sums over the
+// cell's subpoints
+//   q[n3][n4] = sum_sub f(sub, z) sum_v conj(Dv[v][n3]) sum_c x[v][c] Dc[c][n4]
+// in FP64, reading the overlaps and the slice from memory (the cache serves the repeats).
+template <class M2, class V2, int MODE>
+__global__ __launch_bounds__(256) void k_restrict_any(const M2* __restrict__ d, const V2* x, const V2* __restrict__ psi,
+                                                      const double2* __restrict__ P, V2* out,
+                                                      double2* __restrict__ qpart, const ChainState* __restrict__ cs,
+                                                      StepScalars* __restrict__ pend, const double* __restrict__ ppart,
+                                                      double* __restrict__ rpart, double* __restrict__ alpha,
+                                                      double* __restrict__ beta, int lda, int ldb, int step, int n_c,
+                                                      int n_div, int neighbours, int64_t N, int n_rhs, int nv, int nc) {
+    __shared__ double sred[kBlock / kWave];
+    const int np = nv * nc, ne = nv * nv + nc * nc;
+    const int ndiv3 = n_div * n_div * n_div;
+    const int ncells = n_c * n_c * n_c;
+    const int cell = blockIdx.x / n_rhs, rhs = blockIdx.x % n_rhs;
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)rhs * N + (int64_t)cell * ndiv3 * np;
+    const int nelem = ndiv3 * np;
+    double uu = 0.0, pp = 0.0;
+    if (MODE != RESTRICT_PLAIN) {
+        restrict_chain_prefix<V2, MODE>(x, psi, P, out, cs, pend, ppart, alpha, beta, lda, ldb, step, cell, ncells, rhs,
+                                        n_rhs, base, nelem, sred, uu, pp);
+        __syncthreads();  // the block's slice of u is visible to all its threads
+    }
+    const V2* src = (MODE == RESTRICT_PLAIN) ? x : out;
+    for (int o = t; o < 8 * np; o += blockDim.x) {
+        const int z = o / np, pe = o % np, n3 = pe / nc, n4 = pe % nc;
+        const M2* db = d + (int64_t)(cell * 8 + z) * ne * ndiv3;
+        double re = 0.0, im = 0.0;
+        for (int sub = 0; sub < ndiv3; ++sub) {
+            const double f = prefactor(sub, z, n_div, neighbours);
+            if (f == 0.0) continue;
+            const V2* xs = src + base + (int64_t)sub * np;
+            cd y = cmake(0.0, 0.0);
+            for (int v = 0; v < nv; ++v) {
+                cd T = cmake(0.0, 0.0);
+                for (int c = 0; c < nc; ++c) cfma(T, ld(xs + v * nc + c), ld(db + (int64_t)(nv * nv + c * nc + n4) * ndiv3 + sub));
+                cfma_cj(y, ld(db + (int64_t)(v * nv + n3) * ndiv3 + sub), T);
+            }
+            re = fma(f, y.re, re);
+            im = fma(f, y.im, im);
+        }
+        qpart[((int64_t)(cell * 8 + z) * n_rhs + rhs) * np + pe] = make_double2(re, im);
+    }
+    if (MODE == RESTRICT_PLAIN) return;
+    uu = block_sum(uu, sred);
+    pp = block_sum(pp, sred);
+    if (t == 0) {
+        rpart[((int64_t)cell * n_rhs + rhs) * 2] = uu;
+        rpart[((int64_t)cell * n_rhs + rhs) * 2 + 1] = pp;
+    }
+}
+
+template <class M2, class V2>
+hipError_t restrict_any_launch(const Plan& p, int mode, const void* x, const void* w, const void* psi, const double* P,
+                               void* out, int step, double* a, double* b, int lda, int ldb, int n_rhs, hipStream_t s) {
+    const Geometry& g = p.g;
+    double2* qpart = reinterpret_cast<double2*>(p.ws + p.L.qpart);
+    const ChainState* cs = reinterpret_cast<const ChainState*>(p.ws + p.L.chain) + state_in(step) * kMaxRhs;
+    StepScalars* pend = reinterpret_cast<StepScalars*>(p.ws + p.L.pend);
+    const double* ppart = reinterpret_cast<const double*>(p.ws + p.L.ppart);
+    double* rpart = reinterpret_cast<double*>(p.ws + p.L.rpart);
+    const M2* d = reinterpret_cast<const M2*>(p.d);
+    dim3 grid(g.ncells * n_rhs), block(kBlock);
+    if (mode == RESTRICT_PLAIN)
+        hipLaunchKernelGGL((k_restrict_any<M2, V2, RESTRICT_PLAIN>), grid, block, 0, s, d,
+                           reinterpret_cast<const V2*>(x), nullptr, nullptr, nullptr, qpart, cs, pend, ppart, rpart,
+                           nullptr, nullptr, 0, 0, 0, g.n_c, g.n_div, g.neighbours, g.N, n_rhs, g.nv, g.nc);
+    else if (mode == RESTRICT_UPDATE)
+        hipLaunchKernelGGL((k_restrict_any<M2, V2, RESTRICT_UPDATE>), grid, block, 0, s, d,
+                           reinterpret_cast<const V2*>(w), reinterpret_cast<const V2*>(psi), nullptr,
+                           reinterpret_cast<V2*>(out), qpart, cs, pend, ppart, rpart, a, b, lda, ldb, step, g.n_c,
+                           g.n_div, g.neighbours, g.N, n_rhs, g.nv, g.nc);
+    else
+        hipLaunchKernelGGL((k_restrict_any<M2, V2, RESTRICT_INIT>), grid, block, 0, s, d, nullptr, nullptr,
+                           reinterpret_cast<const double2*>(P), reinterpret_cast<V2*>(out), qpart, cs, pend, ppart,
+                           rpart, a, b, lda, ldb, 0, g.n_c, g.n_div, g.neighbours, g.N, n_rhs, g.nv, g.nc);
+    return hipGetLastError();
+}
+
+template hipError_t restrict_any_launch<double2, double2>(const Plan&, int, const void*, const void*, const void*,
+                                                          const double*, void*, int, double*, double*, int, int, int,
+                                                          hipStream_t);
+template hipError_t restrict_any_launch<float2, float2>(const Plan&, int, const void*, const void*, const void*,
+                                                        const double*, void*, int, double*, double*, int, int, int,
+                                                        hipStream_t);
+template hipError_t restrict_any_launch<float2, double2>(const Plan&, int, const void*, const void*, const void*,
+                                                         const double*, void*, int, double*, double*, int, int, int,
+                                                         hipStream_t);
 
 }  // namespace bse

@@ -231,6 +231,41 @@ def test_wide_cell_matvec_and_chain_match_oracle(bse, dtype):
     prob.close()
 
 
+# band pairs without a compiled form: the run-time kernels (restrict and prolong take nv, nc
+# as arguments); 8, 27 and 64 subpoints per cell, up to nv nc = 32 and nv + nc = 16
+ANY_BANDS = [
+    ti.tiny_config(n_coarse=3, n_div=2, nv=2, nc=5, n_orb=7, seed=21, n_pol=3, steps=20),
+    ti.tiny_config(n_coarse=2, n_div=3, nv=5, nc=1, n_orb=6, seed=22, n_pol=2, steps=20),
+    ti.tiny_config(n_coarse=2, n_div=4, nv=4, nc=8, n_orb=12, seed=23, n_pol=1, steps=20),
+    ti.tiny_config(n_coarse=2, n_div=2, nv=2, nc=14, n_orb=16, seed=24, n_pol=2, steps=20),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("cfg", ANY_BANDS, ids=[c.name for c in ANY_BANDS])
+def test_any_band_counts_match_oracle(bse, cfg, dtype):
+    op = oracle_operator(cfg)
+    prob = _problem(bse, cfg, dtype)
+    x = ti.random_vectors(op.N, cfg.n_pol, 111)
+    xs = prob.vector(x)
+    y = prob.matvec(xs).cpu().numpy().astype(complex)
+    ref = op.apply(xs.cpu().numpy().astype(complex))
+    if dtype == "f64":
+        assert rel_l2(y, ref) < 1e-13
+    else:
+        assert np.all(np.abs(y - ref) <= product_bound(op, x, U32, 10, fp32_kernel_factors(True)))
+    # chain start and update forms: the head of the chain
+    P = bands(cfg).P_flat()
+    och = O.haydock(op.apply, P, cfg.steps)
+    ch = prob.haydock(P, cfg.steps)
+    a, b = ch["a"].cpu().numpy(), ch["b"].cpu().numpy()
+    tol = 1e-10 if dtype == "f64" else 1e-5
+    assert np.all(ch["status"].cpu().numpy() == bse.BSE_OK)
+    assert rel_l2(a[:, :10], och["a"][:, :10]) < tol
+    assert rel_l2(b[:, 1:11], och["b"][:, 1:11]) < tol
+    prob.close()
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_restrict_group_gives_same_matvec(bse, dtype):
     # one block per right-hand side, or one block for all three: same arithmetic per

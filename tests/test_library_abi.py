@@ -61,10 +61,16 @@ def test_plan_create_checks_before_device_work(bse):
     # NULL inputs
     st = lib.bse_plan_create(ctypes.byref(d), None, None, None, None, 0, None, ctypes.byref(plan))
     assert st == bse.BSE_ERR_INVALID_ARG
-    # unsupported band counts
-    d2 = bse.Dims(4, 2, 5, 5, 10, 1, bse.BSE_F64, 8)
-    st = lib.bse_plan_create(ctypes.byref(d2), 1, 1, 1, 256, 1 << 30, None, ctypes.byref(plan))
-    assert st == bse.BSE_ERR_UNSUPPORTED
+    # band counts beyond what the hot path takes (nv nc = 35 > 32; nv + nc = 17 > 16)
+    for nv, nc in [(5, 7), (1, 16)]:
+        d2 = bse.Dims(4, 2, nv, nc, nv + nc, 1, bse.BSE_F64, 8)
+        st = lib.bse_plan_create(ctypes.byref(d2), 1, 1, 1, 256, 1 << 30, None, ctypes.byref(plan))
+        assert st == bse.BSE_ERR_UNSUPPORTED
+    # a pair without a compiled form but in range passes the band check (and stops at the
+    # short workspace, before any device work)
+    d3 = bse.Dims(4, 2, 2, 5, 7, 1, bse.BSE_F32, 8)
+    st = lib.bse_plan_create(ctypes.byref(d3), 1, 1, 1, 256, 16, None, ctypes.byref(plan))
+    assert st == bse.BSE_ERR_WORKSPACE
     # misaligned or short workspace
     st = lib.bse_plan_create(ctypes.byref(d), 1, 1, 1, 8, 1 << 30, None, ctypes.byref(plan))
     assert st == bse.BSE_ERR_WORKSPACE
