@@ -186,8 +186,7 @@ bse_status bse_build_coarse_kernel(const bse_dims* dims, const double* vecs_coar
  * Band counts: any nv, nc with nv + nc <= 16 and nv nc <= 32 (else BSE_ERR_UNSUPPORTED).
  * The pairs (1,1) (1,2) (2,2) (2,3) (3,3) (3,4) (3,6) (4,6) run tuned kernels with the
  * counts fixed at compile time; any other pair runs general kernels that take them at
- * run time (FP64 arithmetic, slower) and has no Method 3 band (bse_plan_set_m3_band
- * returns BSE_ERR_UNSUPPORTED for it).
+ * run time (FP64 arithmetic, slower), the Method 3 band product included.
  */
 bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d,
                            const double* delta, void* workspace, size_t workspace_bytes,
@@ -385,7 +384,7 @@ bse_status bse_build_divergence_coefficient(const bse_dims* dims, const double* 
 
 /* Number of band offsets for width w >= 0 and the bytes of the band buffer for dims
  * (BSE_ERR_INVALID_ARG when floor(w n_div) > 16, when 2 floor(w n_div) reaches the
- * dense mesh n_coarse n_div, or when nv nc > 32). */
+ * dense mesh n_coarse n_div, or when nv nc > 32 or nv^2 + nc^2 > 52). */
 bse_status bse_m3_band_info(const bse_dims* dims, double w, int32_t* n_offsets, size_t* band_bytes);
 
 /* Builds the band: the blocks Delta(k, k + o) from the overlaps d (layout of
@@ -403,7 +402,8 @@ bse_status bse_build_m3_band(const bse_dims* dims, const void* d, const void* a_
  * From then on bse_interp_matvec and bse_haydock_run (and batches recorded later)
  * apply H^{M3} = diag(delta) + K^i + Delta: before the prolong, a kernel forms
  * y_k = sum_o Delta(k, k + o) x_{k+o} in FP64, and the prolong adds it.  The band
- * must stay valid while the plan uses it. */
+ * must stay valid while the plan uses it.  BSE_ERR_UNSUPPORTED for band counts beyond
+ * the builder's (nv nc > 32 or nv^2 + nc^2 > 52). */
 bse_status bse_plan_set_m3_band(bse_plan* plan, void* band, double w);
 
 /* Tunables of the coarse product: column splits (0 = automatic).  For sweeps. */

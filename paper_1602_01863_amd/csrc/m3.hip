@@ -413,6 +413,47 @@ static hipError_t m3_apply_go(const Plan& p, const void* x, int n_rhs, hipStream
     return hipGetLastError();
 }
 
+// Band pairs without a compiled form: nv nc at run time, one thread per output entry
+// (k, row n, right-hand side) summing its row of every block in the band, in FP64.
+template <class M2, class V2>
+__global__ __launch_bounds__(256) void k_m3_apply_any(const M2* __restrict__ band, const int4* __restrict__ table,
+                                                      const V2* __restrict__ x, double2* __restrict__ yb, int n_c,
+                                                      int n_div, int n_off_pad, int64_t N, int64_t nk, int np,
+                                                      int n_rhs) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nk * np * n_rhs) return;
+    const int r = (int)(idx % n_rhs);
+    const int64_t rest = idx / n_rhs;
+    const int n = (int)(rest % np);
+    const int64_t k = rest / np;
+    int xk[3];
+    dense_coords(k, n_c, n_div, xk);
+    const M2* bk = band + k * n_off_pad * np * np;
+    cd acc = cmake(0.0, 0.0);
+    for (int c0 = 0; c0 < n_off_pad; c0 += kM3Chunk) {
+        const int W = min(kM3Chunk, n_off_pad - c0);
+        const M2* row = bk + ((int64_t)c0 * np + (int64_t)n * W) * np;   // row n of the chunk: (o_local, m)
+        for (int ol = 0; ol < W; ++ol) {
+            const int4 o = table[c0 + ol];
+            const int xq[3] = {xk[0] + o.x, xk[1] + o.y, xk[2] + o.z};
+            const V2* xr = x + (int64_t)r * N + dense_index(xq, n_c, n_div) * np;
+            for (int m = 0; m < np; ++m) cfma(acc, ld(row + ol * np + m), ld(xr + m));
+        }
+    }
+    yb[(int64_t)r * N + k * np + n] = make_double2(acc.re, acc.im);
+}
+
+template <class M2, class V2>
+static hipError_t m3_apply_any_go(const Plan& p, const void* x, int n_rhs, hipStream_t s) {
+    const Geometry& g = p.g;
+    const M2* band = reinterpret_cast<const M2*>(p.m3_band + up256((size_t)p.m3_noff_pad * sizeof(int4)));
+    const int4* table = reinterpret_cast<const int4*>(p.m3_band);
+    const int64_t total = g.nk * g.np * n_rhs;
+    hipLaunchKernelGGL((k_m3_apply_any<M2, V2>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, band, table,
+                       reinterpret_cast<const V2*>(x), p.m3_yb, g.n_c, g.n_div, p.m3_noff_pad, g.N, g.nk, g.np, n_rhs);
+    return hipGetLastError();
+}
+
 template <int NV, int NC>
 static hipError_t m3_apply_dt(const Plan& p, const void* x, int n_rhs, hipStream_t s) {
     switch (p.g.dtype) {
@@ -435,10 +476,20 @@ hipError_t launch_m3_apply(Plan& p, const void* x, int n_rhs, hipStream_t s) {
     }
     hipError_t err = hipErrorInvalidValue;
     const int nv = p.g.nv, nc = p.g.nc;
+    if (supported_bands(nv, nc)) {
 #define BSE_CASE(a_, b_) \
     if (nv == a_ && nc == b_) err = m3_apply_dt<a_, b_>(p, x, n_rhs, s);
-    BSE_BANDS(BSE_CASE)
+        BSE_BANDS(BSE_CASE)
 #undef BSE_CASE
+    } else {
+        switch (p.g.dtype) {
+            case BSE_F64: err = m3_apply_any_go<double2, double2>(p, x, n_rhs, s); break;
+            case BSE_F32:
+            case BSE_BF16_KC:
+            case BSE_F16_KC: err = m3_apply_any_go<float2, float2>(p, x, n_rhs, s); break;
+            default: err = m3_apply_any_go<float2, double2>(p, x, n_rhs, s); break;
+        }
+    }
     if (e1) (void)hipEventRecord(e1, s);
     return err;
 }
@@ -533,15 +584,15 @@ bse_status bse_plan_set_m3_band(bse_plan* plan, void* band, double w) {
         p.m3_noff_pad = 0;
         return BSE_OK;
     }
+    if (p.g.np > kM3MaxNP || p.g.ne > kM3MaxNE) {   // the builder's limits
+        set_error("bse_plan_set_m3_band: Method 3 takes nv nc <= %d and nv^2 + nc^2 <= %d", kM3MaxNP, kM3MaxNE);
+        return BSE_ERR_UNSUPPORTED;
+    }
     BandLayout L;
     if (!band_layout(p.g, w, &L)) return BSE_ERR_INVALID_ARG;
     if (((uintptr_t)band & 255) != 0) {
         set_error("bse_plan_set_m3_band: band must be 256-byte aligned");
         return BSE_ERR_INVALID_ARG;
-    }
-    if (!supported_bands(p.g.nv, p.g.nc)) {
-        set_error("bse_plan_set_m3_band: bands nv=%d nc=%d are not compiled in", p.g.nv, p.g.nc);
-        return BSE_ERR_UNSUPPORTED;
     }
     p.m3_band = reinterpret_cast<const char*>(band);
     p.m3_yb = reinterpret_cast<double2*>(reinterpret_cast<char*>(band) + L.yb);

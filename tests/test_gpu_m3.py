@@ -119,6 +119,37 @@ def test_m3_matvec_fp64_matches_explicit_kernel(bse, weights):
     prob.close()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_m3_any_band_counts(bse, dtype):
+    """A band pair without a compiled form (2v5c): the run-time band product.  FP64: the
+    library matvec against (diag + K^{M3}) x with K^{M3} written out by the oracle; FP32
+    storage: within the rounding bound of the test below."""
+    cfg = ti.tiny_config(n_coarse=3, n_div=2, nv=2, nc=5, n_orb=7, seed=25, n_pol=2)
+    op, a, Sc, k2, s0 = _oracle_m3(cfg)
+    rng = np.random.default_rng(6)
+    x = rng.normal(size=(2, op.N)) + 1j * rng.normal(size=(2, op.N))
+    prob = bse.problem_from_bands(bands(cfg), cfg, dtype=dtype, max_rhs=2)
+    prob.set_m3(1.0)
+    if dtype == "f64":
+        K3 = O.m3.explicit_kernel(op, a, Sc, 1.0, k2, s0)
+        ref = op.delta[None, :] * x + (K3 @ x.T).T
+        y = prob.matvec(x).cpu().numpy()
+        assert rel_l2(y, ref) < 1e-13
+        assert rel_l2(op.apply(x), ref) > 1e-3   # the band is not a no-op
+    else:
+        x = x.astype(np.complex64).astype(np.complex128)
+        off = O.m3.band_offsets(cfg.n_div, 1.0)
+        sd = O.m3.dense_shape(off, cfg.n_coarse, cfg.n_div, k2, s0)
+        ref = O.m3.apply(op, O.m3.band_blocks(op, a, Sc, off, sd), off, x)
+        aop = abs_operator(op)
+        ablocks = O.m3.band_blocks(aop, np.abs(a).astype(complex), Sc, off, sd, absolute=True)
+        bound = 10 * U32 * np.abs(O.m3.apply(aop, ablocks, off, np.abs(x))) \
+            + (FP32_INNER_UNITS + PACKED_PRODUCT_UNITS) * U32 * np.abs(aop.apply_kernel(np.abs(x)))
+        y = prob.matvec(x).cpu().numpy().astype(np.complex128)
+        assert np.all(np.abs(y - ref) <= bound + 1e-300)
+    prob.close()
+
+
 @pytest.mark.parametrize("cfg,w", [
     (ti.tiny_config(n_coarse=3, n_div=2, nv=3, nc=6, n_orb=9, seed=21, n_pol=3), 1.0),
     (ti.tiny_config(n_coarse=2, n_div=3, nv=2, nc=3, n_orb=6, seed=22, n_pol=2), 0.7),
