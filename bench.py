@@ -87,6 +87,8 @@ def _args():
                    help="batching workload: 48 uneven Hamiltonians x 3 polarisations in one HIP graph")
     p.add_argument("--batch-launches", type=int, default=3, help="timed graph launches of the batch")
     p.add_argument("--no-autotune", action="store_true", help="batch: keep the automatic tunables")
+    p.add_argument("--no-batch", action="store_true",
+                   help="leave the batching workload out of the default line")
     p.add_argument("--time-to-spectrum", action="store_true",
                    help="time to eps2 of the plain FP32 form against the BF16 form, its graph-recorded "
                         "chains and the learned terminator (C1 workload)")
@@ -330,15 +332,30 @@ def main():
         if m3 is not None:
             out["cpu_baseline"] = m3_cpu_baseline(cfg, args.m3, out["cpu_baseline"])
     prob.close()
+    if not args.no_batch and args.m3 is None:
+        # the batching workload (48 Hamiltonians, 144 chains in HIP graphs), summarised
+        del prob
+        torch.cuda.empty_cache()
+        b = run_batch(args, with_cpu=False)
+        out["batch"] = {k: b[k] for k in ("metric", "value", "unit", "batch_s", "per_chain_steps_per_s",
+                                          "graph_launches_per_batch", "sequential_host_launched_s",
+                                          "speedup_vs_sequential", "chain_status", "inputs_s")}
+        out["batch"]["workload"] = b["config"]["workload"]
+        out["batch"]["roofline_frac"] = b["roofline"]["frac"] if b["roofline"] else None
     print(json.dumps(out), flush=True)
 
 
 def batch_bench(args):
+    """The batching workload on its own: one JSON line (see run_batch)."""
+    print(json.dumps(run_batch(args, with_cpu=not args.no_cpu_baseline)), flush=True)
+
+
+def run_batch(args, with_cpu):
     """48 uneven Hamiltonians (16 displaced structures x 3 grids, nv 3, nc 3 or 6) with 3
     polarisations each = 144 Haydock chains of 200 steps, recorded once into a HIP graph
-    and launched as one unit; tunables picked per shape by the autotuner.  Prints one
-    JSON line with the aggregate and per-chain rates and the same chains run one plan
-    after the other without the graph."""
+    and launched as one unit; tunables picked per shape by the autotuner.  Returns the
+    aggregate and per-chain rates and the same chains run one plan after the other
+    without the graph."""
     import torch
 
     import tbinputs as ti
@@ -409,7 +426,7 @@ def batch_bench(args):
         "sequential_host_launched_s": round(t_eager, 4),
         "speedup_vs_sequential": round(t_eager / t_batch, 3),
         "roofline": batch_roofline(cfgs, probs, steps, t_batch),
-        "cpu_baseline": None if args.no_cpu_baseline else batch_cpu_baseline(cfgs, bss, steps),
+        "cpu_baseline": batch_cpu_baseline(cfgs, bss, steps) if with_cpu else None,
         "chain_status": status,
         "autotuned": shapes,
         "inputs_s": round(t_inputs, 1), "setup_s": round(t_setup, 2), "tune_s": round(t_tune, 2),
@@ -417,18 +434,20 @@ def batch_bench(args):
     batch.close()
     for p in probs:
         p.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def batch_roofline(cfgs, probs, steps, t_batch):
-    """Aggregate algorithmic HBM bytes of every member's steps (K_c once, the overlaps
-    in prolong and restrict, the Lanczos vectors, the transition energies) over the
-    batch time, against the HBM peak."""
+    """Aggregate algorithmic HBM bytes of every member's steps (the packed K_c tiles on and
+    above the diagonal once, the overlaps in prolong and restrict, the Lanczos vectors, the
+    transition energies) over the batch time, against the HBM peak."""
     total = 0.0
     for c, p in zip(cfgs, probs):
         ne = c.nv ** 2 + c.nc ** 2
         d_bytes = c.nk_coarse * 8 * ne * c.n_div3 * 8
-        step = p.Nc * p.Nc * 8 + 2 * p.Nc * c.n_pol * 16 + 2 * d_bytes + c.n_pol * p.N * 8 * 6 + p.N * 8
+        nbk = (p.Nc + 127) // 128
+        kc_bytes = nbk * (nbk + 1) // 2 * 128 * 128 * 8   # FP32 members: packed Hermitian tiles
+        step = kc_bytes + 2 * p.Nc * c.n_pol * 16 + 2 * d_bytes + c.n_pol * p.N * 8 * 6 + p.N * 8
         total += step * steps
     ach = total / t_batch / 1e9
     return {"kernel": "all step kernels of the 48 members (aggregate)", "bound": "hbm",
