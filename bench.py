@@ -48,17 +48,18 @@ def measured_m3_traffic(workload: str, dtype: str, w: float):
     return int(m_t.group(1)) if digest == m_h.group(1) else None
 
 
-def measured_traffic(workload: str, dtype: str):
-    """HBM bytes per coarse-product launch from the committed rocprofv3 counter
-    summary, or None if it does not cover this workload or the kernel source has
-    changed since the counters were taken."""
+def measured_traffic(workload: str, dtype: str, key: str = "traffic_bytes_per_launch"):
+    """HBM bytes per launch (key: the coarse product's two kernels, or
+    traffic_bytes_per_launch_stream for its streaming kernel alone) from the committed
+    rocprofv3 counter summary, or None if it does not cover this workload or the kernel
+    source has changed since the counters were taken."""
     import hashlib
     import re
 
     if workload != "c1" or dtype != "f32" or not os.path.exists(COUNTER_SUMMARY):
         return None
     text = open(COUNTER_SUMMARY).read()
-    m_t = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    m_t = re.search(key + r":\s*(\d+)", text)
     m_h = re.search(r"gemv_source_sha256_16:\s*([0-9a-f]+)", text)
     if not (m_t and m_h):
         return None
@@ -157,6 +158,15 @@ def main():
     gemv_ms_total, gemv_launches = prob.timing()
     prob.set_timing(False)
     gemv_ms = gemv_ms_total / max(1, gemv_launches)
+    # the same for the product's streaming kernel alone (events closed before the kernel
+    # that adds its partials): the dominant kernel of the step
+    prob.set_timing(3)
+    torch.cuda.synchronize()
+    prob.haydock(P, args.steps)
+    torch.cuda.synchronize()
+    kern_ms_total, kern_launches = prob.timing()
+    prob.set_timing(False)
+    kern_ms = kern_ms_total / max(1, kern_launches)
 
     # ---- warmup, then exactly K timed steps (one chain run of K steps)
     if args.warmup > 0:
@@ -195,6 +205,10 @@ def main():
     gemv_bytes = kc_bytes + 2 * Nc * n_rhs * 16                  # K_c once + qbar in + r out
     gemv_flops = 8.0 * Nc * Nc * n_rhs                           # complex MAC = 8 flops
     achieved_gbs = gemv_bytes / (gemv_ms * 1e-3) / 1e9
+    kern_bytes = kc_bytes + Nc * n_rhs * 16                      # the streaming kernel: K_c once + qbar in
+    kern_gbs = kern_bytes / (kern_ms * 1e-3) / 1e9
+    kern_name = ("k_hemv_mfma" if lowp and packed else "k_gemv_mfma" if lowp
+                 else "k_hemv64" if packed and dtype == "f64" else "k_hemv" if packed else "k_gemv2")
     # matrix-core work actually issued: per 64 x 64 block and 16-row group, four 16x16x32
     # products (16 columns: 4 rhs x re/im x leading/remainder)
     # issued 16x16x32 products: 16 per stored block for P1, 16 more per off-diagonal block
@@ -293,21 +307,26 @@ def main():
             else "VALU FP64 FMA on " + ("FP64" if dtype == "f64" else "FP32") + " storage (HBM-bound; no MFMA)",
             "MFMA_TFLOPs_issued": round(mfma_flops / (gemv_ms * 1e-3) / 1e12, 3) if lowp else None,
             "MFMA_peak_TFLOPs": 2500.0 if lowp else None,
-        },
-        "roofline": {
-            "kernel": ("coarse product r = K_c qbar, packed Hermitian blocks (k_hemv_mfma + k_hm_reduce)"
-                       if lowp and packed
-                       else "coarse product r = K_c qbar (k_gemv_mfma + k_gemv_reduce)" if lowp
-                       else "coarse product r = K_c qbar, packed Hermitian tiles (k_hemv64 + k_hemv_reduce)"
-                       if packed and dtype == "f64"
-                       else "coarse product r = K_c qbar, packed Hermitian tiles (k_hemv + k_hemv_reduce)"
-                       if packed else "coarse product r = K_c qbar (k_gemv2 + k_gemv_reduce)"),
-            "bound": "hbm",
-            "achieved": round(achieved_gbs, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
+            "span": ("k_hemv_mfma + k_hm_reduce" if lowp and packed else "k_gemv_mfma + k_gemv_reduce" if lowp
+                     else "k_hemv64 + k_hemv_reduce" if packed and dtype == "f64"
+                     else "k_hemv + k_hemv_reduce" if packed else "k_gemv2 + k_gemv_reduce"),
+            "algorithmic_bytes": int(gemv_bytes),
+            "GBps": round(achieved_gbs, 1),
             "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args.config, dtype),
+        },
+        "roofline": {
+            "kernel": f"{kern_name}: the coarse product's streaming kernel (r = K_c qbar"
+                      + (", packed Hermitian " + ("blocks" if lowp else "tiles") if packed else "")
+                      + "), without the kernel that adds its partials",
+            "bound": "hbm",
+            "achieved": round(kern_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(kern_gbs / HBM_PEAK_GBS, 4),
+            "avg_ms": round(kern_ms, 5),
+            "algorithmic_bytes": int(kern_bytes),
+            "traffic": measured_traffic(args.config, dtype, "traffic_bytes_per_launch_stream"),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },
         "method3": m3,

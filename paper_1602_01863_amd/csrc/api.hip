@@ -454,6 +454,7 @@ bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d, 
     p->ev = nullptr;
     p->ev_cap = 0;
     p->ev_used = 0;
+    p->split_ev = nullptr;
     p->timed_ms = 0.0;
     p->timed_launches = 0;
     // restrict tiles: a re-ordered copy of the overlaps in the workspace; for the
@@ -621,7 +622,7 @@ bse_status bse_plan_set_timing(bse_plan* plan, int32_t enable) {
         p.ev_cap = cap;
     }
     if (!enable) release_events(&p);
-    p.timing = enable == 2 ? 2 : (enable != 0 ? 1 : 0);
+    p.timing = (enable == 2 || enable == 3) ? enable : (enable != 0 ? 1 : 0);
     p.ev_used = 0;
     p.timed_ms = 0.0;
     p.timed_launches = 0;

@@ -130,13 +130,15 @@ struct Plan {
     int n_split;  // 0 = automatic
     int product_form;  // coarse product of the FP32/FP64 coarse kernel: 0 packed Hermitian tiles, 1 full stream
     int restrict_group;  // right-hand sides per restrict block (1, or 3 for three)
-    // kernel timing: 0 off, 1 the coarse product, 2 the Method 3 band product
+    // kernel timing: 0 off, 1 the coarse product, 2 the Method 3 band product, 3 the coarse
+    // product's streaming kernel alone
     int timing;
     int ev_used;
     double timed_ms;
     int64_t timed_launches;
     hipEvent_t* ev;
     int ev_cap;
+    hipEvent_t split_ev;   // timing mode 3: recorded right after the product's streaming kernel
     // Method 3 band (m3.hip); m3_band == nullptr: Method 1 only
     const char* m3_band;  // caller's band buffer: offset table, then the blocks
     double2* m3_yb;       // band product [rhs][N] (FP64), the tail of the band buffer

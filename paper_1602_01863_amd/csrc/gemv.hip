@@ -22,6 +22,12 @@
 
 namespace bse {
 
+// kernel timing mode 3: the event that closes the timed span, recorded on the product's
+// stream right after its streaming kernel (before the kernel that adds the partials)
+static inline void mark_stream_end(const Plan& p, hipStream_t s) {
+    if (p.split_ev) (void)hipEventRecord(p.split_ev, s);
+}
+
 template <class M2>
 struct Gv;
 template <>
@@ -255,6 +261,7 @@ static hipError_t gemv_t(Plan& p, hipStream_t s) {
                            n_rowblk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    mark_stream_end(p, s);
     const int64_t n_out = g.Nc * NRHS;
     hipLaunchKernelGGL(k_gemv_reduce, dim3((unsigned)((n_out + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, part, rvec,
                        n_out, n_split);
@@ -717,6 +724,7 @@ static hipError_t hemv_lowp(Plan& p, int n_rhs, hipStream_t s) {
                            h.run_len, p1, p2, h.nb, n_rhs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    mark_stream_end(p, s);
     const int64_t n_thr = g.Nc * n_rhs * 8;
     const dim3 rg((unsigned)((n_thr + kBlock - 1) / kBlock)), rblock(kBlock);
     const double2* q1 = reinterpret_cast<const double2*>(p1);
@@ -756,6 +764,7 @@ static hipError_t gemv_lowp(Plan& p, int n_rhs, hipStream_t s) {
                            n_rhs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    mark_stream_end(p, s);
     const int64_t n_out = g.Nc * n_rhs;
     hipLaunchKernelGGL(k_gemv_reduce, dim3((unsigned)((n_out + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                        reinterpret_cast<const double2*>(part), rvec, n_out, ns);
@@ -1260,6 +1269,7 @@ static hipError_t hemv_t(Plan& p, hipStream_t s) {
                            h.tpw);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
+        mark_stream_end(p, s);
         hipLaunchKernelGGL((k_hemv_reduce<NRHS, double2>), rgrid, dim3(kBlock), 0, s, r1, r2, tab + h.blocks, rvec,
                            (int)g.Nc, h.nbk);
         return hipGetLastError();
@@ -1273,6 +1283,7 @@ static hipError_t hemv_t(Plan& p, hipStream_t s) {
                        reinterpret_cast<const f4v*>(p.ws + p.L.kp), qbar, tab, r1, r2, (int)g.Nc, h.nbk, h.tpw);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    mark_stream_end(p, s);
     hipLaunchKernelGGL((k_hemv_reduce<NRHS, float2>), rgrid, dim3(kBlock), 0, s, r1, r2, tab + h.blocks, rvec,
                        (int)g.Nc, h.nbk);
     return hipGetLastError();
@@ -1299,17 +1310,20 @@ static hipError_t gemv_r(Plan& p, int n_rhs, hipStream_t s) {
 
 hipError_t launch_gemv(Plan& p, int n_rhs, hipStream_t s) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (p.timing == 1 && p.ev && p.ev_used + 2 <= p.ev_cap) {
+    if ((p.timing == 1 || p.timing == 3) && p.ev && p.ev_used + 2 <= p.ev_cap) {
         e0 = p.ev[p.ev_used];
         e1 = p.ev[p.ev_used + 1];
         p.ev_used += 2;
         (void)hipEventRecord(e0, s);
     }
+    // mode 3 closes the span after the streaming kernel, mode 1 after the whole product
+    p.split_ev = p.timing == 3 ? e1 : nullptr;
     hipError_t err = kc_lowp(p.g.dtype)        ? gemv_lowp(p, n_rhs, s)
                      : use_packed(p)          ? hemv_r(p, n_rhs, s)
                      : (p.g.dtype == BSE_F64) ? gemv_r<double2>(p, n_rhs, s)
                                               : gemv_r<float2>(p, n_rhs, s);
-    if (e1) (void)hipEventRecord(e1, s);
+    if (e1 && p.timing == 1) (void)hipEventRecord(e1, s);
+    p.split_ev = nullptr;
     return err;
 }
 
