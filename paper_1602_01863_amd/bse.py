@@ -549,8 +549,10 @@ class BSEProblem:
         bse_plan_set_m3_band(self.plan, self.band, w)
         self.m3_offsets = n_off
 
-    def set_timing(self, enable: bool):
-        bse_plan_set_timing(self.plan, enable)
+    def set_timing(self, enable):
+        """0 off; 1 (or True) the coarse product; 2 the Method 3 band product; 3 the coarse
+        product's streaming kernel alone."""
+        bse_plan_set_timing(self.plan, int(enable))
 
     def timing(self):
         return bse_plan_get_timing(self.plan)

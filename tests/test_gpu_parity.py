@@ -266,6 +266,26 @@ def test_any_band_counts_match_oracle(bse, cfg, dtype):
     prob.close()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64", "bf16"])
+def test_kernel_timing_modes(bse, dtype):
+    """Plan timing: one event pair per coarse product of a chain step, around the whole
+    product (mode 1) or its streaming kernel alone (mode 3); timing does not change the
+    chain's coefficients."""
+    cfg = ti.get_config("c0")
+    prob = _problem(bse, cfg, dtype)
+    P = bands(cfg).P_flat()
+    ref = prob.haydock(P, 12)
+    for mode in (1, 3):
+        prob.set_timing(mode)
+        ch = prob.haydock(P, 12)
+        ms, n = prob.timing()
+        prob.set_timing(0)
+        assert n == 12 and ms > 0.0
+        assert np.array_equal(ch["a"].cpu().numpy(), ref["a"].cpu().numpy())
+        assert np.array_equal(ch["b"].cpu().numpy(), ref["b"].cpu().numpy())
+    prob.close()
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_restrict_group_gives_same_matvec(bse, dtype):
     # one block per right-hand side, or one block for all three: same arithmetic per
