@@ -133,17 +133,24 @@ constexpr int prolong3_waves() {
     return (sizeof(M2) == 8 && sizeof(V2) == 8 && NV * NC <= 18 && !(NV == 3 && NC == 4) && NR < 4) ? 3 : 2;
 }
 
-// threads of a block: 2 wavefronts per right-hand side, at least 4 wavefronts (the
-// extra ones only help staging)
-template <int NR>
+// threads of a block: NPART wavefronts per right-hand side (each takes 1 / NPART of the
+// conduction index c), at least 4 wavefronts (the extra ones only help staging)
+template <int NR, int NPART>
 constexpr int prolong3_threads() {
-    return 128 * (NR < 2 ? 2 : NR);
+    return kWave * (NR * NPART < 4 ? 4 : NR * NPART);
+}
+// wavefronts per right-hand side: 3 for band pairs above 18 products with several
+// right-hand sides (4v6c: 100 VGPRs instead of 132, two 9-wavefront blocks per compute
+// unit; 100.4 against 105.6 us at 10^3 x 4^3 cells), else 2
+template <int NV, int NC, int NR>
+constexpr int prolong3_parts() {
+    return (NV * NC > 18 && NR >= 2) ? 3 : 2;
 }
 
 // NDIV3 > 0: the subpoint count n_div^3 fixed at compile time (the LDS offsets of the
 // corner loop become immediates); 0: taken from n_div
-template <class M2, class V2, int NV, int NC, int MODE, int NR, int NDIV3>
-__global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, V2, NV, NC, NR>())) void k_prolong3(const M2* __restrict__ d, const double* __restrict__ delta,
+template <class M2, class V2, int NV, int NC, int MODE, int NR, int NDIV3, int NPART>
+__global__ __launch_bounds__((prolong3_threads<NR, NPART>()), (prolong3_waves<M2, V2, NV, NC, NR>())) void k_prolong3(const M2* __restrict__ d, const double* __restrict__ delta,
                                                          const double2* __restrict__ rvec, const V2* __restrict__ x,
                                                          V2* __restrict__ out, double* __restrict__ ppart,
                                                          const ChainState* __restrict__ chain, int n_c, int n_div,
@@ -151,8 +158,8 @@ __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, V2, NV,
                                                          const double2* __restrict__ yb) {
     constexpr int NP = NV * NC;
     constexpr int NE = NV * NV + NC * NC;
-    constexpr int NCH = (NC + 1) / 2;
-    constexpr int NT = prolong3_threads<NR>();
+    constexpr int NCH = (NC + NPART - 1) / NPART;
+    constexpr int NT = prolong3_threads<NR, NPART>();
     using U = Unit16<M2>;
     using Rw = typename U::t;
     constexpr int PFU = (NE * kWave / U::P + NT - 1) / NT;  // staged 16-byte units per thread (n_div^3 <= 64)
@@ -171,8 +178,8 @@ __global__ __launch_bounds__(prolong3_threads<NR>(), (prolong3_waves<M2, V2, NV,
     const int t = threadIdx.x;
     const int wave = t / kWave;
     const int lane = t % kWave;
-    const int rhs = wave >> 1;
-    const int h = wave & 1;
+    const int rhs = wave / NPART;
+    const int h = wave % NPART;
     const bool active = lane < ndiv3 && rhs < NR;
 
     // coarse blocks r_{k~z} of the 8 corners (rs[z][p][r]), the overlaps of corner 0 and
@@ -433,15 +440,16 @@ static void prolong3_go(const Plan& p, int mode, const V2* xv, V2* ov, const Cha
     double* ppart = reinterpret_cast<double*>(p.ws + p.L.ppart);
     const M2* d = reinterpret_cast<const M2*>(p.d);
     const double2* yb = p.m3_band ? p.m3_yb : nullptr;
-    dim3 grid(g.ncells), block(prolong3_threads<NR>());
+    constexpr int NPART = prolong3_parts<NV, NC, NR>();
+    dim3 grid(g.ncells), block(prolong3_threads<NR, NPART>());
     if (mode == PROLONG_PLAIN)
-        hipLaunchKernelGGL((k_prolong3<M2, V2, NV, NC, PROLONG_PLAIN, NR, 0>), grid, block, lds, s, d, p.delta, rvec,
+        hipLaunchKernelGGL((k_prolong3<M2, V2, NV, NC, PROLONG_PLAIN, NR, 0, NPART>), grid, block, lds, s, d, p.delta, rvec,
                            xv, ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, yb);
     else if (g.ndiv3 == 64)   // 4 divisions per axis, the chain's common case
-        hipLaunchKernelGGL((k_prolong3<M2, V2, NV, NC, PROLONG_LANCZOS, NR, 64>), grid, block, lds, s, d, p.delta,
+        hipLaunchKernelGGL((k_prolong3<M2, V2, NV, NC, PROLONG_LANCZOS, NR, 64, NPART>), grid, block, lds, s, d, p.delta,
                            rvec, xv, ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, yb);
     else
-        hipLaunchKernelGGL((k_prolong3<M2, V2, NV, NC, PROLONG_LANCZOS, NR, 0>), grid, block, lds, s, d, p.delta,
+        hipLaunchKernelGGL((k_prolong3<M2, V2, NV, NC, PROLONG_LANCZOS, NR, 0, NPART>), grid, block, lds, s, d, p.delta,
                            rvec, xv, ov, ppart, cs, g.n_c, g.n_div, g.neighbours, g.N, yb);
 }
 
@@ -459,7 +467,7 @@ hipError_t prolong_launch(const Plan& p, int mode, const void* x, void* out, int
     // staged form: whole 16-byte units per (cell, corner) block and an aligned base
     const bool units = ((size_t)NE * g.ndiv3 * sizeof(M2)) % 16 == 0 && ((uintptr_t)p.d & 15) == 0;
     // prefactor table, per-wavefront chain partials (at most 2 kMaxRhs wavefronts)
-    const size_t static_lds = 8 * kWave * sizeof(double) + kMaxRhs * (2 * kMaxRhs) * 2 * sizeof(double);
+    const size_t static_lds = 8 * kWave * sizeof(double) + kMaxRhs * (3 * kMaxRhs) * 2 * sizeof(double);
     if (g.ndiv3 <= kWave && lds + static_lds <= lds_limit() && units) {
         switch (n_rhs) {
             case 1: prolong3_go<M2, V2, NV, NC, 1>(p, mode, xv, ov, cs, lds, s); break;

@@ -231,6 +231,35 @@ def test_wide_cell_matvec_and_chain_match_oracle(bse, dtype):
     prob.close()
 
 
+# 4v6c with three right-hand sides: the prolong splits the conduction index over three
+# wavefronts per right-hand side
+WIDE_BANDS = ti.tiny_config(n_coarse=2, n_div=4, nv=4, nc=6, n_orb=10, seed=26, n_pol=3, steps=20)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_wide_band_pair_three_rhs_matches_oracle(bse, dtype):
+    cfg = WIDE_BANDS
+    op = oracle_operator(cfg)
+    prob = _problem(bse, cfg, dtype)
+    x = ti.random_vectors(op.N, 3, 112)
+    xs = prob.vector(x)
+    y = prob.matvec(xs).cpu().numpy().astype(complex)
+    ref = op.apply(xs.cpu().numpy().astype(complex))
+    if dtype == "f64":
+        assert rel_l2(y, ref) < 1e-13
+    else:
+        assert np.all(np.abs(y - ref) <= product_bound(op, x, U32, 10, fp32_kernel_factors(True)))
+    P = bands(cfg).P_flat()
+    och = O.haydock(op.apply, P, cfg.steps)
+    ch = prob.haydock(P, cfg.steps)
+    a, b = ch["a"].cpu().numpy(), ch["b"].cpu().numpy()
+    tol = 1e-10 if dtype == "f64" else 1e-5
+    assert np.all(ch["status"].cpu().numpy() == bse.BSE_OK)
+    assert rel_l2(a[:, :10], och["a"][:, :10]) < tol
+    assert rel_l2(b[:, 1:11], och["b"][:, 1:11]) < tol
+    prob.close()
+
+
 # band pairs without a compiled form: the run-time kernels (restrict and prolong take nv, nc
 # as arguments); 8, 27 and 64 subpoints per cell, up to nv nc = 32 and nv + nc = 16
 ANY_BANDS = [
