@@ -23,6 +23,8 @@ MEMBERS = [
     (ti.tiny_config(n_coarse=2, n_div=4, nv=4, nc=6, n_orb=10, seed=14, n_pol=2), "bf16"),
     (ti.tiny_config(n_coarse=2, n_div=5, nv=2, nc=3, n_orb=5, seed=12, n_pol=4), "f32v64"),
     (ti.tiny_config(n_coarse=4, n_div=2, nv=3, nc=3, n_orb=9, seed=3, n_pol=3, perturb=(0.01, 1000)), "f32"),
+    # a band pair without a compiled form: the run-time restrict and prolong in the graphs
+    (ti.tiny_config(n_coarse=3, n_div=2, nv=2, nc=5, n_orb=7, seed=21, n_pol=3), "f32"),
 ]
 
 
