@@ -129,6 +129,7 @@ Layout make_layout(const Geometry& g) {
     L.chain = take((size_t)2 * kMaxRhs * sizeof(ChainState));
     L.pend = take((size_t)kMaxRhs * sizeof(StepScalars));
     L.flags = take((size_t)kMaxRhs * sizeof(int32_t));
+    L.cpart = take((size_t)kMaxRhs * kConvBlocks * 2 * sizeof(double));
     L.vec_a = take((size_t)g.N * R * vec_elem_bytes(g.dtype));
     L.vec_b = take((size_t)g.N * R * vec_elem_bytes(g.dtype));
     L.kq = L.kscale = L.qfrag = L.qsinv = L.mp1 = L.mp2 = L.mtab = off;
@@ -257,13 +258,17 @@ hipError_t enqueue_haydock(Plan& p, const double* P, int n_rhs, int n_steps, dou
 // with the previous check's eps2 at every omega.  A chain whose largest change is at most
 // tol times the largest |eps2| stops: its state is made inactive (status BSE_OK), so the
 // following steps leave its coefficients alone.  active_out[r] = chain still running.
-__global__ __launch_bounds__(1024) void k_converge_check(const double* __restrict__ a, const double* __restrict__ b,
-                                                         int lda, int ldb, ChainState* __restrict__ cs, double prefactor,
-                                                         const double* __restrict__ omega, int n_omega, double eta,
-                                                         double tol, int first, int closure,
-                                                         double* __restrict__ eps_re, double* __restrict__ eps_im,
-                                                         int32_t* __restrict__ active_out) {
-    __shared__ double sred[2][1024 / kWave];
+// Block (chain r, slice q) of the convergence check: eps_M at the frequencies
+// w = q blockDim + thread, stride gridDim.y blockDim, from the chain's first m coefficients,
+// and the slice's largest change since the last check and largest |eps2|, written to
+// part[(r nq + q) 2 + {0, 1}] for k_converge_decide.
+__global__ __launch_bounds__(256) void k_converge_check(const double* __restrict__ a, const double* __restrict__ b,
+                                                        int lda, int ldb, const ChainState* __restrict__ cs,
+                                                        double prefactor, const double* __restrict__ omega,
+                                                        int n_omega, double eta, int first, int closure,
+                                                        double* __restrict__ eps_re, double* __restrict__ eps_im,
+                                                        double* __restrict__ part) {
+    __shared__ double sred[2][256 / kWave];
     const int r = blockIdx.x;
     const ChainState st = cs[r];
     const int m = min(st.steps, lda);
@@ -283,7 +288,7 @@ __global__ __launch_bounds__(1024) void k_converge_check(const double* __restric
         bm2 = bc[m] * bc[m];   // b_{m+1}: 0 after a breakdown, which leaves the fraction exact
     }
     double dmax = 0.0, emax = 0.0;
-    for (int w = threadIdx.x; w < n_omega; w += blockDim.x) {
+    for (int w = blockIdx.y * blockDim.x + threadIdx.x; w < n_omega; w += gridDim.y * blockDim.x) {
         double er = 1.0, ei = 0.0;
         if (m > 0 && pn != 0.0) {
             const double zr = omega[w], zi = eta;
@@ -325,13 +330,30 @@ __global__ __launch_bounds__(1024) void k_converge_check(const double* __restric
             dmax = fmax(dmax, sred[0][w]);
             emax = fmax(emax, sred[1][w]);
         }
-        int active = st.active;
-        if (active && !first && dmax <= tol * emax) {
-            cs[r].active = 0;   // converged: the chain stops here with status BSE_OK
-            active = 0;
-        }
-        active_out[r] = active;
+        double* o = part + ((int64_t)r * gridDim.y + blockIdx.y) * 2;
+        o[0] = dmax;
+        o[1] = emax;
     }
+}
+
+// The stop rule of each chain from the slices' maxima (a maximum does not depend on the
+// order of its terms): a chain whose spectrum changed by at most tol times its peak since
+// the last check stops.  Thread r < n_rhs.
+__global__ void k_converge_decide(const double* __restrict__ part, int nq, ChainState* __restrict__ cs, double tol,
+                                  int first, int n_rhs, int32_t* __restrict__ active_out) {
+    const int r = threadIdx.x;
+    if (r >= n_rhs) return;
+    double dmax = 0.0, emax = 0.0;
+    for (int q = 0; q < nq; ++q) {
+        dmax = fmax(dmax, part[((int64_t)r * nq + q) * 2]);
+        emax = fmax(emax, part[((int64_t)r * nq + q) * 2 + 1]);
+    }
+    int active = cs[r].active;
+    if (active && !first && dmax <= tol * emax) {
+        cs[r].active = 0;   // converged: the chain stops here with status BSE_OK
+        active = 0;
+    }
+    active_out[r] = active;
 }
 
 }  // namespace bse
@@ -560,9 +582,16 @@ bse_status bse_haydock_converge(bse_plan* plan, const double* P, int32_t n_rhs, 
         i += n;
         if (e != hipSuccess) break;
         ChainState* cs = reinterpret_cast<ChainState*>(p.ws + p.L.chain) + state_in(i) * kMaxRhs;
-        hipLaunchKernelGGL(k_converge_check, dim3(n_rhs), dim3(1024), 0, stream, a, b, lda, ldb, cs, prefactor, omega,
-                           n_omega, eta, tol, c == 0 ? 1 : 0, p.converge_closure, eps_re, eps_im, flags);
+        // the check over the frequencies in slices of 256, then the stop decision per chain
+        const int nq = std::min(kConvBlocks, (n_omega + 255) / 256);
+        double* cpart = reinterpret_cast<double*>(p.ws + p.L.cpart);
+        hipLaunchKernelGGL(k_converge_check, dim3(n_rhs, nq), dim3(256), 0, stream, a, b, lda, ldb, cs, prefactor,
+                           omega, n_omega, eta, c == 0 ? 1 : 0, p.converge_closure, eps_re, eps_im, cpart);
         e = hipGetLastError();
+        if (e == hipSuccess)
+            hipLaunchKernelGGL(k_converge_decide, dim3(1), dim3(kWave), 0, stream, cpart, nq, cs, tol,
+                               c == 0 ? 1 : 0, n_rhs, flags);
+        if (e == hipSuccess) e = hipGetLastError();
         if (e == hipSuccess) e = hipEventRecord(p.chk[c & 1], stream);
         // the previous check is read while this chunk runs: at most one chunk past the
         // convergence is enqueued, and it leaves the stopped chains unchanged

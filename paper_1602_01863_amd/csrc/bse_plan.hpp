@@ -11,6 +11,7 @@ namespace bse {
 
 constexpr int kMaxRhs = 4;
 constexpr int kMaxSplit = 64;        // column splits of the coarse product
+constexpr int kConvBlocks = 64;      // blocks per chain of the convergence check (at most)
 constexpr int kBlock = 256;          // threads of the reduction / product blocks
 
 // Per-chain Lanczos state kept on the device between kernels.  The chain stores
@@ -113,7 +114,7 @@ inline bool kc_packable(int dtype) { return dtype == BSE_F32 || dtype == BSE_F32
 // form's qbar scales) and mp1, mp2, mtab (partials and run table of their packed product)
 // only for the low-precision forms; kp, hpart, htab only for the FP32 and FP64 coarse kernels
 struct Layout {
-    size_t qpart, qbar, rvec, gpart, ppart, rpart, chain, pend, flags, vec_a, vec_b, dsw, kq, kscale, qfrag, qsinv, kp,
+    size_t qpart, qbar, rvec, gpart, ppart, rpart, chain, pend, flags, cpart, vec_a, vec_b, dsw, kq, kscale, qfrag, qsinv, kp,
         hpart, htab, mp1, mp2, mtab;
     size_t dsw_bytes, kq_bytes, kscale_bytes, qfrag_bytes, kp_bytes;
     size_t total;
