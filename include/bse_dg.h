@@ -238,9 +238,10 @@ bse_status bse_haydock_run(bse_plan* plan, const double* P, int32_t n_rhs, int32
  *   omega      device FP64 [n_omega]
  *   eps_re, eps_im  device FP64 [n_rhs][n_omega]: eps_M of the last check (the converged
  *              spectrum), also the previous spectrum between checks
- * The host reads one flag per check while the next check_every steps run, so at most one
- * chunk past the convergence of the last chain is enqueued (it leaves the stopped chains
- * unchanged).  The call returns after the stream has finished the run.
+ * The host reads one flag per chain at each check while the first 4 steps of the next
+ * chunk run, so at most 4 steps past the convergence of the last chain are enqueued (they
+ * leave the stopped chains unchanged).  The call returns after the stream has finished the
+ * run.
  */
 bse_status bse_haydock_converge(bse_plan* plan, const double* P, int32_t n_rhs, int32_t max_steps,
                                 int32_t check_every, double prefactor, const double* omega,

@@ -574,11 +574,12 @@ bse_status bse_haydock_converge(bse_plan* plan, const double* P, int32_t n_rhs, 
         if (!p.chk[k]) e = hipEventCreateWithFlags(&p.chk[k], hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "bse_haydock_converge: stream or events");
     e = enqueue_chain_start(p, P, n_rhs, a, b, lda, ldb, stream);
-    int i = 0, c = 0;
+    // i: steps up to the last check; ahead: steps past i already enqueued
+    int i = 0, ahead = 0, c = 0;
     bool running = true;
     while (e == hipSuccess && i < max_steps) {
         const int n = std::min(check_every, max_steps - i);
-        e = enqueue_chain_steps(p, i, i + n, n_rhs, a, b, lda, ldb, stream);
+        if (ahead < n) e = enqueue_chain_steps(p, i + ahead, i + n, n_rhs, a, b, lda, ldb, stream);
         i += n;
         if (e != hipSuccess) break;
         ChainState* cs = reinterpret_cast<ChainState*>(p.ws + p.L.chain) + state_in(i) * kMaxRhs;
@@ -593,18 +594,23 @@ bse_status bse_haydock_converge(bse_plan* plan, const double* P, int32_t n_rhs, 
                                c == 0 ? 1 : 0, n_rhs, flags);
         if (e == hipSuccess) e = hipGetLastError();
         if (e == hipSuccess) e = hipEventRecord(p.chk[c & 1], stream);
-        // the previous check is read while this chunk runs: at most one chunk past the
-        // convergence is enqueued, and it leaves the stopped chains unchanged
-        if (e == hipSuccess && c > 0) {
+        // the first steps of the next chunk keep the device busy while the host reads this
+        // check; once every chain has stopped they leave the chains unchanged
+        ahead = std::min(kConvAhead, std::min(check_every, max_steps - i));
+        if (e == hipSuccess && ahead > 0) e = enqueue_chain_steps(p, i, i + ahead, n_rhs, a, b, lda, ldb, stream);
+        if (e == hipSuccess) {
             int32_t act[kMaxRhs] = {0, 0, 0, 0};
-            e = hipEventSynchronize(p.chk[(c - 1) & 1]);
+            e = hipEventSynchronize(p.chk[c & 1]);
             if (e == hipSuccess) e = hipMemcpyAsync(act, flags, n_rhs * sizeof(int32_t), hipMemcpyDeviceToHost, p.side);
             if (e == hipSuccess) e = hipStreamSynchronize(p.side);
             running = false;
             for (int r = 0; r < n_rhs; ++r) running = running || act[r] != 0;
         }
         ++c;
-        if (!running) break;
+        if (!running) {
+            i += ahead;
+            break;
+        }
     }
     if (e == hipSuccess) e = launch_chain_report(p, i, pnorm2, steps_done, status, n_rhs, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);

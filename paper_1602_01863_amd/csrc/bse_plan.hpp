@@ -12,6 +12,7 @@ namespace bse {
 constexpr int kMaxRhs = 4;
 constexpr int kMaxSplit = 64;        // column splits of the coarse product
 constexpr int kConvBlocks = 64;      // blocks per chain of the convergence check (at most)
+constexpr int kConvAhead = 4;        // chain steps enqueued past a convergence check before its flags are read
 constexpr int kBlock = 256;          // threads of the reduction / product blocks
 
 // Per-chain Lanczos state kept on the device between kernels.  The chain stores

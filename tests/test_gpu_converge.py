@@ -124,3 +124,26 @@ def test_closed_convergence_matches_the_oracle_and_stops_no_later(bse):
     oeps = O.continued_fraction(och["a"], och["b"], och["pnorm2"], C, om, eta)
     assert rel_l2(eps.imag, oeps.imag) < 10 * tol
     prob.close()
+
+
+@pytest.mark.parametrize("every", [1, 3, 5, 40])
+def test_unconverged_run_is_the_fixed_length_chain(bse, every):
+    """tol = 0 never stops a chain, so it runs to max_steps (37, not a multiple of the check
+    interval: the last chunk is short; the interval 1 checks after every step, 40 exceeds
+    the whole run): the coefficients, norms and status are the fixed-length run's bit for
+    bit, whatever steps were enqueued ahead of each check, and the spectrum is Eq.
+    (fraccont) of all 37 coefficients."""
+    cfg = ti.get_config("c0")
+    prob = bse.problem_from_bands(bands(cfg), cfg, dtype="f64", max_rhs=1)
+    P = bands(cfg).P_flat()[:1]
+    om = cfg.omega()
+    n = 37
+    ch, eps = prob.haydock_converge(P, n, om, 0.3, cfg.prefactor(), 0.0, check_every=every)
+    ch = _host(ch)
+    full = _host(prob.haydock(P, n))
+    for k in ("a", "b", "pnorm2", "steps", "status"):
+        assert np.array_equal(ch[k], full[k]), k
+    assert ch["steps"][0] == n
+    e_n = O.continued_fraction(ch["a"], ch["b"], ch["pnorm2"], cfg.prefactor(), om, 0.3)
+    assert rel_l2(eps.cpu().numpy().imag, e_n.imag) < 1e-12
+    prob.close()
