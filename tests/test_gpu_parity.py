@@ -267,6 +267,9 @@ ANY_BANDS = [
     ti.tiny_config(n_coarse=2, n_div=3, nv=5, nc=1, n_orb=6, seed=22, n_pol=2, steps=20),
     ti.tiny_config(n_coarse=2, n_div=4, nv=4, nc=8, n_orb=12, seed=23, n_pol=1, steps=20),
     ti.tiny_config(n_coarse=2, n_div=2, nv=2, nc=14, n_orb=16, seed=24, n_pol=2, steps=20),
+    # the other ends of the range: eight valence bands, and a single one with 15 conduction
+    ti.tiny_config(n_coarse=2, n_div=2, nv=8, nc=4, n_orb=12, seed=25, n_pol=1, steps=20),
+    ti.tiny_config(n_coarse=2, n_div=3, nv=1, nc=15, n_orb=16, seed=26, n_pol=2, steps=20),
 ]
 
 
