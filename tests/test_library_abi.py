@@ -95,6 +95,12 @@ def test_other_entry_points_check_arguments(bse):
     assert lib.bse_plan_set_restrict_group(None, 1) == bse.BSE_ERR_INVALID_ARG
     assert lib.bse_plan_set_coarse_product(None, 0) == bse.BSE_ERR_INVALID_ARG
     assert lib.bse_plan_set_converge_closure(None, 16) == bse.BSE_ERR_INVALID_ARG
+    # converged chains: NULL plan, then NULL outputs, before any device work
+    conv = [1, 3, 100, 20, 1.0, 1, 10, 0.1, 1e-3] + [1] * 7 + [None]
+    assert lib.bse_haydock_converge(None, *conv) == bse.BSE_ERR_INVALID_ARG
+    conv_null_eps = conv[:14] + [None, None, None]
+    assert lib.bse_haydock_converge(1, *conv_null_eps) == bse.BSE_ERR_INVALID_ARG
+    assert lib.bse_batch_launch(None, None) == bse.BSE_ERR_INVALID_ARG
 
 
 def test_m3_band_geometry_and_checks(bse):
