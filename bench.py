@@ -158,8 +158,8 @@ def main():
     gemv_ms_total, gemv_launches = prob.timing()
     prob.set_timing(False)
     gemv_ms = gemv_ms_total / max(1, gemv_launches)
-    # the same for the product's streaming kernel alone (events closed before the kernel
-    # that adds its partials): the dominant kernel of the step
+    # the product's streaming kernel alone, the dominant kernel of the step: the library
+    # launches it with an event pair that the runtime stamps with its own start and end
     prob.set_timing(3)
     torch.cuda.synchronize()
     prob.haydock(P, args.steps)

@@ -265,8 +265,9 @@ bse_status bse_continued_fraction(const double* a, const double* b, int32_t lda,
 /* Kernel timing: with enable = 1 the plan records HIP events around every launch
  * of the coarse product (the dominant kernel of Method 1: the split product and
  * the kernel that adds its splits) on the stream it is launched on; with enable = 3
- * around its streaming kernel alone (the events close before the kernel that adds the
- * partials); with enable = 2 around every launch of the Method 3 band product instead;
+ * it times the product's streaming kernel alone, by launching it with an event pair
+ * that the runtime stamps with that kernel's own start and end (hipExtLaunchKernel);
+ * with enable = 2 around every launch of the Method 3 band product instead;
  * 0 turns timing off.
  * bse_plan_get_timing synchronises those events and returns the total time in
  * milliseconds and the number of timed launches since the last reset. */

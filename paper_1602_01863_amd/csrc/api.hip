@@ -476,7 +476,7 @@ bse_status bse_plan_create(const bse_dims* dims, const void* Kc, const void* d, 
     p->ev = nullptr;
     p->ev_cap = 0;
     p->ev_used = 0;
-    p->split_ev = nullptr;
+    p->split_start = p->split_ev = nullptr;
     p->timed_ms = 0.0;
     p->timed_launches = 0;
     // restrict tiles: a re-ordered copy of the overlaps in the workspace; for the

@@ -140,7 +140,7 @@ struct Plan {
     int64_t timed_launches;
     hipEvent_t* ev;
     int ev_cap;
-    hipEvent_t split_ev;   // timing mode 3: recorded right after the product's streaming kernel
+    hipEvent_t split_start, split_ev;   // timing mode 3: the pair the streaming kernel's launch stamps
     // Method 3 band (m3.hip); m3_band == nullptr: Method 1 only
     const char* m3_band;  // caller's band buffer: offset table, then the blocks
     double2* m3_yb;       // band product [rhs][N] (FP64), the tail of the band buffer

@@ -13,6 +13,7 @@
 // wavefront partials are added in LDS in a fixed order and every block writes its
 // split partial; k_gemv_reduce then adds the splits of each output in a fixed order.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,10 +23,17 @@
 
 namespace bse {
 
-// kernel timing mode 3: the event that closes the timed span, recorded on the product's
-// stream right after its streaming kernel (before the kernel that adds the partials)
-static inline void mark_stream_end(const Plan& p, hipStream_t s) {
-    if (p.split_ev) (void)hipEventRecord(p.split_ev, s);
+// Launch of a coarse product's streaming kernel (the kernel before the one that adds the
+// partials).  In kernel timing mode 3 the launch itself carries the event pair: the runtime
+// stamps the two events with that kernel's own start and end, so the timed span holds the
+// kernel alone, without the gap that an event recorded between two launches puts in front.
+template <typename F, typename... Args>
+static inline void launch_stream(const Plan& p, F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                                 Args... args) {
+    if (p.split_ev)
+        hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)lds, s, p.split_start, p.split_ev, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
 }
 
 template <class M2>
@@ -248,20 +256,19 @@ static hipError_t gemv_t(Plan& p, hipStream_t s) {
     dim3 grid(n_rowblk * n_split), block(kBlock);
     const bool multi = chunk > kGemvLdsCols / NRHS;
     if (vec && !multi)
-        hipLaunchKernelGGL((k_gemv2<M2, NRHS, true, false>), grid, block, lds, s, K, qbar, part, (int)g.Nc, chunk,
+        launch_stream(p, (k_gemv2<M2, NRHS, true, false>), grid, block, lds, s, K, qbar, part, (int)g.Nc, chunk,
                            n_rowblk);
     else if (vec)
-        hipLaunchKernelGGL((k_gemv2<M2, NRHS, true, true>), grid, block, lds, s, K, qbar, part, (int)g.Nc, chunk,
+        launch_stream(p, (k_gemv2<M2, NRHS, true, true>), grid, block, lds, s, K, qbar, part, (int)g.Nc, chunk,
                            n_rowblk);
     else if (!multi)
-        hipLaunchKernelGGL((k_gemv2<M2, NRHS, false, false>), grid, block, lds, s, K, qbar, part, (int)g.Nc, chunk,
+        launch_stream(p, (k_gemv2<M2, NRHS, false, false>), grid, block, lds, s, K, qbar, part, (int)g.Nc, chunk,
                            n_rowblk);
     else
-        hipLaunchKernelGGL((k_gemv2<M2, NRHS, false, true>), grid, block, lds, s, K, qbar, part, (int)g.Nc, chunk,
+        launch_stream(p, (k_gemv2<M2, NRHS, false, true>), grid, block, lds, s, K, qbar, part, (int)g.Nc, chunk,
                            n_rowblk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    mark_stream_end(p, s);
     const int64_t n_out = g.Nc * NRHS;
     hipLaunchKernelGGL(k_gemv_reduce, dim3((unsigned)((n_out + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, part, rvec,
                        n_out, n_split);
@@ -717,14 +724,13 @@ static hipError_t hemv_lowp(Plan& p, int n_rhs, hipStream_t s) {
     const dim3 grid((unsigned)((h.runs + wpb - 1) / wpb)), block(kHmBlock);
     const size_t lds = (size_t)wpb * 2 * 64 * kHmPitch * sizeof(unsigned short);
     if (g.dtype == BSE_BF16_KC)
-        hipLaunchKernelGGL(k_hemv_mfma<BSE_BF16_KC>, grid, block, lds, s, kq, ksc, qf, qsi, runs, (int)h.runs,
+        launch_stream(p, k_hemv_mfma<BSE_BF16_KC>, grid, block, lds, s, kq, ksc, qf, qsi, runs, (int)h.runs,
                            h.run_len, p1, p2, h.nb, n_rhs);
     else
-        hipLaunchKernelGGL(k_hemv_mfma<BSE_F16_KC>, grid, block, lds, s, kq, ksc, qf, qsi, runs, (int)h.runs,
+        launch_stream(p, k_hemv_mfma<BSE_F16_KC>, grid, block, lds, s, kq, ksc, qf, qsi, runs, (int)h.runs,
                            h.run_len, p1, p2, h.nb, n_rhs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    mark_stream_end(p, s);
     const int64_t n_thr = g.Nc * n_rhs * 8;
     const dim3 rg((unsigned)((n_thr + kBlock - 1) / kBlock)), rblock(kBlock);
     const double2* q1 = reinterpret_cast<const double2*>(p1);
@@ -757,14 +763,13 @@ static hipError_t gemv_lowp(Plan& p, int n_rhs, hipStream_t s) {
     double2* rvec = reinterpret_cast<double2*>(p.ws + p.L.rvec);
     dim3 grid((unsigned)(k.nb * ns)), block(kBlock);
     if (g.dtype == BSE_BF16_KC)
-        hipLaunchKernelGGL(k_gemv_mfma<BSE_BF16_KC>, grid, block, 0, s, kq, ksc, qf, qsi, part, (int)g.Nc, k.nb, cpb,
+        launch_stream(p, k_gemv_mfma<BSE_BF16_KC>, grid, block, 0, s, kq, ksc, qf, qsi, part, (int)g.Nc, k.nb, cpb,
                            n_rhs);
     else
-        hipLaunchKernelGGL(k_gemv_mfma<BSE_F16_KC>, grid, block, 0, s, kq, ksc, qf, qsi, part, (int)g.Nc, k.nb, cpb,
+        launch_stream(p, k_gemv_mfma<BSE_F16_KC>, grid, block, 0, s, kq, ksc, qf, qsi, part, (int)g.Nc, k.nb, cpb,
                            n_rhs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    mark_stream_end(p, s);
     const int64_t n_out = g.Nc * n_rhs;
     hipLaunchKernelGGL(k_gemv_reduce, dim3((unsigned)((n_out + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                        reinterpret_cast<const double2*>(part), rvec, n_out, ns);
@@ -1264,12 +1269,11 @@ static hipError_t hemv_t(Plan& p, hipStream_t s) {
         double2* r2 = r1 + (size_t)h.blocks * kHemvTile * NRHS;
         // q_J of 4 wavefronts x 64 columns, or the P1 sums of 4 x 128 rows
         const size_t lds = (size_t)4 * kHemvTile * NRHS * sizeof(double2);
-        hipLaunchKernelGGL((k_hemv64<NRHS>), dim3((unsigned)h.blocks), dim3(kBlock), lds, s,
+        launch_stream(p, (k_hemv64<NRHS>), dim3((unsigned)h.blocks), dim3(kBlock), lds, s,
                            reinterpret_cast<const d2v*>(p.ws + p.L.kp), qbar, tab, r1, r2, (int)g.Nc, h.nbk,
                            h.tpw);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        mark_stream_end(p, s);
         hipLaunchKernelGGL((k_hemv_reduce<NRHS, double2>), rgrid, dim3(kBlock), 0, s, r1, r2, tab + h.blocks, rvec,
                            (int)g.Nc, h.nbk);
         return hipGetLastError();
@@ -1279,11 +1283,10 @@ static hipError_t hemv_t(Plan& p, hipStream_t s) {
     // q_J and P2 sums of 4 wavefronts x 64 columns, or the P1 sums of 4 x 128 rows
     const size_t lds = std::max((size_t)4 * NRHS * 64 * (sizeof(float2) + sizeof(double2)),
                                 (size_t)4 * kHemvTile * NRHS * sizeof(double2));
-    hipLaunchKernelGGL((k_hemv<NRHS>), dim3((unsigned)h.blocks), dim3(kBlock), lds, s,
+    launch_stream(p, (k_hemv<NRHS>), dim3((unsigned)h.blocks), dim3(kBlock), lds, s,
                        reinterpret_cast<const f4v*>(p.ws + p.L.kp), qbar, tab, r1, r2, (int)g.Nc, h.nbk, h.tpw);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    mark_stream_end(p, s);
     hipLaunchKernelGGL((k_hemv_reduce<NRHS, float2>), rgrid, dim3(kBlock), 0, s, r1, r2, tab + h.blocks, rvec,
                        (int)g.Nc, h.nbk);
     return hipGetLastError();
@@ -1314,16 +1317,18 @@ hipError_t launch_gemv(Plan& p, int n_rhs, hipStream_t s) {
         e0 = p.ev[p.ev_used];
         e1 = p.ev[p.ev_used + 1];
         p.ev_used += 2;
-        (void)hipEventRecord(e0, s);
+        if (p.timing == 1) (void)hipEventRecord(e0, s);
     }
-    // mode 3 closes the span after the streaming kernel, mode 1 after the whole product
+    // mode 1 times the whole product between two recorded events; mode 3 hands the pair to
+    // the launch of the streaming kernel (launch_stream)
+    p.split_start = p.timing == 3 ? e0 : nullptr;
     p.split_ev = p.timing == 3 ? e1 : nullptr;
     hipError_t err = kc_lowp(p.g.dtype)        ? gemv_lowp(p, n_rhs, s)
                      : use_packed(p)          ? hemv_r(p, n_rhs, s)
                      : (p.g.dtype == BSE_F64) ? gemv_r<double2>(p, n_rhs, s)
                                               : gemv_r<float2>(p, n_rhs, s);
     if (e1 && p.timing == 1) (void)hipEventRecord(e1, s);
-    p.split_ev = nullptr;
+    p.split_start = p.split_ev = nullptr;
     return err;
 }
 
