@@ -299,11 +299,11 @@ __global__ __launch_bounds__(256) void k_converge_check(const double* __restrict
                 tr -= bm2 * gr;
                 ti -= bm2 * gi;
             }
-            for (int j = m - 2; j >= 0; --j) {
+            for (int j = m - 2; j >= 0; --j) {   // t_j = z - a_j - b_{j+1}^2 / t_{j+1}
                 const double b2 = bc[j + 1] * bc[j + 1];
-                const double den = tr * tr + ti * ti;
-                tr = zr - ac[j] - b2 * tr / den;
-                ti = zi + b2 * ti / den;
+                const double g = b2 / (tr * tr + ti * ti);   // one division per level
+                tr = zr - ac[j] - g * tr;
+                ti = zi + g * ti;
             }
             const double den = tr * tr + ti * ti;
             er = 1.0 - prefactor * pn * tr / den;
