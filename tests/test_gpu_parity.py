@@ -301,20 +301,24 @@ def test_any_band_counts_match_oracle(bse, cfg, dtype):
 @pytest.mark.parametrize("dtype", ["f32", "f64", "bf16"])
 def test_kernel_timing_modes(bse, dtype):
     """Plan timing: one event pair per coarse product of a chain step, around the whole
-    product (mode 1) or its streaming kernel alone (mode 3); timing does not change the
-    chain's coefficients."""
+    product (mode 1) or carried by the launch of its streaming kernel alone (mode 3, which
+    cannot take longer than the whole product); timing does not change the chain's
+    coefficients."""
     cfg = ti.get_config("c0")
     prob = _problem(bse, cfg, dtype)
     P = bands(cfg).P_flat()
     ref = prob.haydock(P, 12)
+    per_launch = {}
     for mode in (1, 3):
         prob.set_timing(mode)
         ch = prob.haydock(P, 12)
         ms, n = prob.timing()
         prob.set_timing(0)
         assert n == 12 and ms > 0.0
+        per_launch[mode] = ms / n
         assert np.array_equal(ch["a"].cpu().numpy(), ref["a"].cpu().numpy())
         assert np.array_equal(ch["b"].cpu().numpy(), ref["b"].cpu().numpy())
+    assert per_launch[3] < per_launch[1]
     prob.close()
 
 
