@@ -298,14 +298,16 @@ def test_any_band_counts_match_oracle(bse, cfg, dtype):
     prob.close()
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f64", "bf16"])
-def test_kernel_timing_modes(bse, dtype):
+@pytest.mark.parametrize("dtype,form", [("f32", 0), ("f64", 0), ("bf16", 0), ("f16", 0), ("f32", 1), ("bf16", 1)],
+                         ids=["f32", "f64", "bf16", "f16", "f32-full", "bf16-full"])
+def test_kernel_timing_modes(bse, dtype, form):
     """Plan timing: one event pair per coarse product of a chain step, around the whole
     product (mode 1) or carried by the launch of its streaming kernel alone (mode 3, which
     cannot take longer than the whole product); timing does not change the chain's
     coefficients."""
     cfg = ti.get_config("c0")
     prob = _problem(bse, cfg, dtype)
+    bse.bse_plan_set_coarse_product(prob.plan, form)   # 1: the full-stream product
     P = bands(cfg).P_flat()
     ref = prob.haydock(P, 12)
     per_launch = {}
